@@ -1,0 +1,188 @@
+"""CPU oracle for the Swendsen-Wang sweep (test infrastructure only).
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg
+of ``bench.py`` may import this package.  It wraps ``sw_oracle.c`` -- a plain
+sequential C implementation written from the paper's Sec. 2 (bond formation,
+cluster formation, assignment of new spins, measurement) -- through ctypes.
+It shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sw_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# Record layout of ``orc_obs`` (sw_oracle.h).
+OBS_DTYPE = np.dtype(
+    [
+        ("sweep", "<u8"),
+        ("e_sum", "<i8"),
+        ("energy", "<f8"),
+        ("m_sum", "<i8"),
+        ("n_clusters", "<u8"),
+        ("max_cluster", "<u8"),
+        ("sum_sq_sizes", "<u8"),
+        ("hist_log2", "<u8", (33,)),
+    ]
+)
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc -O2 (plain C, one thread)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+             "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        l = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, u32, u64, i64, f64 = (ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
+                                   ctypes.c_int64, ctypes.c_double)
+        l.orc_philox4x32_10.argtypes = [P, P, P]
+        l.orc_philox4x32_10.restype = None
+        l.orc_threshold.argtypes = [f64, f64]
+        l.orc_threshold.restype = u32
+        l.orc_init.argtypes = [i32, u64, i32, P]
+        l.orc_init.restype = None
+        l.orc_bonds.argtypes = [i32, u32, u64, u32, P, P]
+        l.orc_bonds.restype = None
+        l.orc_label.argtypes = [i32, P, P]
+        l.orc_label.restype = None
+        l.orc_flip_spin.argtypes = [u64, u32, u32]
+        l.orc_flip_spin.restype = i32
+        l.orc_assign.argtypes = [i32, u64, u32, P, P]
+        l.orc_assign.restype = None
+        l.orc_observe.argtypes = [i32, f64, u64, P, P, P, P]
+        l.orc_observe.restype = None
+        l.orc_sweep.argtypes = [i32, f64, u32, u64, u32, P, P, P, P, P]
+        l.orc_sweep.restype = ctypes.c_int
+        l.orc_run.argtypes = [i32, f64, u32, u64, u32, i64, P, P]
+        l.orc_run.restype = ctypes.c_int
+        l.orc_chains.argtypes = [i32, f64, u32, u64, i64, i32, P, P]
+        l.orc_chains.restype = ctypes.c_int
+        l.orc_one_step_codes.argtypes = [i32, u32, u64, i64, u32, P, P]
+        l.orc_one_step_codes.restype = ctypes.c_int
+        _lib = l
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def threshold(beta: float, J: float = 1.0) -> int:
+    return int(lib().orc_threshold(beta, J))
+
+
+def init(L: int, seed: int, cold: bool = False) -> np.ndarray:
+    s = np.empty(L * L, dtype=np.int8)
+    lib().orc_init(L, seed, 1 if cold else 0, _p(s))
+    return s
+
+
+def bonds(L: int, T: int, seed: int, t: int, spins: np.ndarray) -> np.ndarray:
+    sp = np.ascontiguousarray(spins, dtype=np.int8)
+    b = np.empty(L * L, dtype=np.uint8)
+    lib().orc_bonds(L, T, seed, t, _p(sp), _p(b))
+    return b
+
+
+def label(L: int, bond_mask: np.ndarray) -> np.ndarray:
+    b = np.ascontiguousarray(bond_mask, dtype=np.uint8)
+    lab = np.empty(L * L, dtype=np.uint32)
+    lib().orc_label(L, _p(b), _p(lab))
+    return lab
+
+
+def flip_spin(seed: int, t: int, root: int) -> int:
+    return int(lib().orc_flip_spin(seed, t, root))
+
+
+def assign(L: int, seed: int, t: int, labels: np.ndarray) -> np.ndarray:
+    lab = np.ascontiguousarray(labels, dtype=np.uint32)
+    s = np.empty(L * L, dtype=np.int8)
+    lib().orc_assign(L, seed, t, _p(lab), _p(s))
+    return s
+
+
+def observe(L: int, J: float, sweep: int, spins: np.ndarray, labels=None,
+            dense: bool = False):
+    sp = np.ascontiguousarray(spins, dtype=np.int8)
+    lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.uint32)
+    rec = np.zeros(1, dtype=OBS_DTYPE)
+    d = np.zeros(L * L + 1, dtype=np.uint64) if dense else None
+    lib().orc_observe(L, J, sweep, _p(sp), _p(lab), _p(rec), _p(d))
+    return (rec[0], d) if dense else rec[0]
+
+
+def sweep(L: int, J: float, T: int, seed: int, t: int, spins: np.ndarray,
+          dense: bool = False):
+    """One sweep in place on ``spins``; returns (record, labels, bonds[, dense])."""
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous and spins.size == L * L
+    lab = np.empty(L * L, dtype=np.uint32)
+    b = np.empty(L * L, dtype=np.uint8)
+    rec = np.zeros(1, dtype=OBS_DTYPE)
+    d = np.zeros(L * L + 1, dtype=np.uint64) if dense else None
+    rc = lib().orc_sweep(L, J, T, seed, t, _p(spins), _p(lab), _p(b), _p(rec), _p(d))
+    if rc != 0:
+        raise MemoryError("oracle sweep: allocation failed")
+    if dense:
+        return rec[0], lab, b, d
+    return rec[0], lab, b
+
+
+def run(L: int, J: float, T: int, seed: int, t0: int, count: int,
+        spins: np.ndarray) -> np.ndarray:
+    """``count`` sweeps in place on ``spins``; returns their records."""
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous and spins.size == L * L
+    recs = np.zeros(count, dtype=OBS_DTYPE)
+    rc = lib().orc_run(L, J, T, seed, t0, count, _p(spins), _p(recs))
+    if rc != 0:
+        raise MemoryError("oracle run: allocation failed")
+    return recs
+
+
+def chains(L: int, J: float, T: int, seed0: int, nchains: int, nsweeps: int):
+    e = np.zeros(nchains, dtype=np.int64)
+    m = np.zeros(nchains, dtype=np.int64)
+    rc = lib().orc_chains(L, J, T, seed0, nchains, nsweeps, _p(e), _p(m))
+    if rc != 0:
+        raise MemoryError("oracle chains: allocation failed")
+    return e, m
+
+
+def one_step_codes(L: int, T: int, seed0: int, nseeds: int, t: int,
+                   start: np.ndarray) -> np.ndarray:
+    st = np.ascontiguousarray(start, dtype=np.int8)
+    codes = np.zeros(nseeds, dtype=np.uint64)
+    rc = lib().orc_one_step_codes(L, T, seed0, nseeds, t, _p(st), _p(codes))
+    if rc != 0:
+        raise ValueError("oracle one_step_codes: lattice too large")
+    return codes

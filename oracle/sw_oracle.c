@@ -1,0 +1,317 @@
+/*
+ * sw_oracle.c -- plain, sequential CPU oracle for one Swendsen-Wang sweep of
+ * the 2D Ising model on an L x L periodic square lattice.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * generator with the HIP library; it is written to be read against the paper
+ * (Protzman & Giedt, "GPU Acceleration of Swendson-Wang Dynamics"), not to be
+ * fast.
+ *
+ * Conventions fixed here (the paper is silent on all of them; the readings
+ * are listed in the design notes):
+ *   site index        s = y*L + x, x fastest, 0 <= x,y < L, periodic.
+ *   E(s)              y*L + (x+1 mod L)          (direction d = 0)
+ *   N(s)              ((y+1) mod L)*L + x        (direction d = 1)
+ *   Each site owns the two edges to E(s) and N(s), so all 2N torus edges are
+ *   visited exactly once (Sec. 2.1: a thread checks two of its four
+ *   neighbours; Fig. 2 caption).
+ *   Spins are int8 +1 / -1.  Labels are uint32 (min site index of the
+ *   cluster, Sec. 2.3 "lowest value label" with initial label = site index).
+ *
+ * Randomness (the paper names no generator, Sec. 2.1 only says "a random
+ * number is generated"): counter-based Philox4x32-10, key = seed, with a
+ * domain tag in counter word 2:
+ *   bonds  : w(s,d) = word 2*(s&1)+d of Philox({s>>1, t, 0, 0})
+ *   flips  : bit (r mod 128) of the 128-bit Philox({r>>7, t, 1, 0}) output,
+ *            i.e. word (r>>5)&3, bit r&31;  bit 1 -> spin -1, bit 0 -> +1
+ *   init   : bit 0 of word 0 of Philox({s, 0, 2, 0}); 1 -> -1, 0 -> +1
+ *
+ * Parity pins (all in the CPU test-suite): Philox known-answer vectors,
+ * the closed form of the bond threshold at beta_c, brute-force BFS labels,
+ * exact enumeration of the 4x4 torus, exact one-sweep transition rows of the
+ * 2x2 and 3x3 tori, the Ferdinand-Fisher finite-size energy at beta_c, the
+ * Onsager energy off criticality, and integer invariants.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "sw_oracle.h"
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, Sec. 4.1):        */
+/* each round multiplies counter words 0 and 2 by two fixed odd        */
+/* constants, swaps in the high halves xor-ed with the other counter   */
+/* words and the round key; the key is advanced by the Weyl constants  */
+/* (golden ratio and sqrt(3)-1) between rounds.                        */
+/* ------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                       uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod_a = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t prod_b = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t hi_a = (uint32_t)(prod_a >> 32), lo_a = (uint32_t)prod_a;
+        uint32_t hi_b = (uint32_t)(prod_b >> 32), lo_b = (uint32_t)prod_b;
+        x0 = hi_b ^ x1 ^ k0;
+        x1 = lo_b;
+        x2 = hi_a ^ x3 ^ k1;
+        x3 = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static void philox_seed(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                        uint32_t out[4])
+{
+    uint32_t ctr[4] = {c0, c1, c2, 0u};
+    uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------ */
+/* Bond probability (Sec. 2.1).  The printed p = 1 - exp(-1/kT) puts   */
+/* T_c near 1.13, contradicting the paper's own T_c ~ 2.25 (Sec. 4);   */
+/* the reading used is p = 1 - exp(-2 beta J), evaluated once in FP64  */
+/* and turned into a 32-bit threshold so that P(bond) = T / 2^32.      */
+/* ------------------------------------------------------------------ */
+uint32_t orc_threshold(double beta, double J)
+{
+    double p = -expm1(-2.0 * beta * J);
+    if (!(p > 0.0)) return 0u;
+    double scaled = floor(ldexp(p, 32));
+    if (scaled >= 4294967296.0) return 0xFFFFFFFFu;
+    return (uint32_t)scaled;
+}
+
+/* Initial configuration (Fig. 1): hot = i.i.d. +-1 with probability 1/2,
+ * cold = all +1. */
+void orc_init(int32_t L, uint64_t seed, int32_t cold, int8_t *spins)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    for (uint32_t s = 0; s < n; ++s) {
+        if (cold) { spins[s] = 1; continue; }
+        uint32_t r[4];
+        philox_seed(seed, s, 0u, 2u, r);
+        spins[s] = (r[0] & 1u) ? (int8_t)-1 : (int8_t)1;
+    }
+}
+
+static uint32_t east_of(uint32_t s, uint32_t L)
+{
+    uint32_t x = s % L, y = s / L;
+    return y * L + (x + 1u) % L;
+}
+
+static uint32_t north_of(uint32_t s, uint32_t L)
+{
+    uint32_t x = s % L, y = s / L;
+    return ((y + 1u) % L) * L + x;
+}
+
+/* Sec. 2.1, Bond formation: an edge is bonded iff both ends carry the same
+ * spin and the edge's uniform 32-bit word is below the threshold.
+ * bonds[s] bit 0 = bond (s, E(s)), bit 1 = bond (s, N(s)). */
+void orc_bonds(int32_t L, uint32_t T, uint64_t seed, uint32_t t,
+               const int8_t *spins, uint8_t *bonds)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    for (uint32_t s = 0; s < n; ++s) {
+        uint32_t r[4];
+        philox_seed(seed, s >> 1, t, 0u, r);
+        uint32_t wE = r[2u * (s & 1u) + 0u];
+        uint32_t wN = r[2u * (s & 1u) + 1u];
+        uint8_t b = 0;
+        if (spins[s] == spins[east_of(s, (uint32_t)L)] && wE < T) b |= 1u;
+        if (spins[s] == spins[north_of(s, (uint32_t)L)] && wN < T) b |= 2u;
+        bonds[s] = b;
+    }
+}
+
+/* Sec. 2.3, Cluster formation: connected components of the bond graph.
+ * Textbook sequential union-find; the root of every set is kept at the
+ * smallest site index of the set, so after the final find every site
+ * carries the lowest label of its cluster. `labels` doubles as the
+ * parent array. */
+static uint32_t uf_find(uint32_t *parent, uint32_t a)
+{
+    while (parent[a] != a) {
+        parent[a] = parent[parent[a]];
+        a = parent[a];
+    }
+    return a;
+}
+
+static void uf_union(uint32_t *parent, uint32_t a, uint32_t b)
+{
+    uint32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
+    if (ra == rb) return;
+    if (ra < rb) parent[rb] = ra;
+    else parent[ra] = rb;
+}
+
+void orc_label(int32_t L, const uint8_t *bonds, uint32_t *labels)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    for (uint32_t s = 0; s < n; ++s) labels[s] = s;
+    for (uint32_t s = 0; s < n; ++s) {
+        if (bonds[s] & 1u) uf_union(labels, s, east_of(s, (uint32_t)L));
+        if (bonds[s] & 2u) uf_union(labels, s, north_of(s, (uint32_t)L));
+    }
+    for (uint32_t s = 0; s < n; ++s) labels[s] = uf_find(labels, s);
+}
+
+/* Sec. 2.4, Assignment of new spins: every cluster draws a fresh spin,
+ * up or down with probability 1/2, independent of its old spin; the draw is
+ * keyed by the cluster's canonical (minimum-site) label. */
+int32_t orc_flip_spin(uint64_t seed, uint32_t t, uint32_t root)
+{
+    uint32_t r[4];
+    philox_seed(seed, root >> 7, t, 1u, r);
+    uint32_t bit = (r[(root >> 5) & 3u] >> (root & 31u)) & 1u;
+    return bit ? -1 : 1;
+}
+
+void orc_assign(int32_t L, uint64_t seed, uint32_t t, const uint32_t *labels,
+                int8_t *spins)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    for (uint32_t s = 0; s < n; ++s)
+        spins[s] = (int8_t)orc_flip_spin(seed, t, labels[s]);
+}
+
+/* Sec. 2.5 measurement: H = -J sum_<ij> s_i s_j over the 2N torus edges,
+ * M = sum_i s_i (the paper divides by N; the exact integer sum is kept and
+ * divided at the end).  Cluster statistics come from the labels of the
+ * sweep's bonds.  `dense` (may be NULL) receives counts[size] for
+ * size = 0..N. */
+void orc_observe(int32_t L, double J, uint64_t sweep, const int8_t *spins,
+                 const uint32_t *labels, orc_obs *rec, uint64_t *dense)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    int64_t e = 0, m = 0;
+    for (uint32_t s = 0; s < n; ++s) {
+        int32_t si = spins[s];
+        e += si * spins[east_of(s, (uint32_t)L)];
+        e += si * spins[north_of(s, (uint32_t)L)];
+        m += si;
+    }
+    memset(rec, 0, sizeof(*rec));
+    rec->sweep = sweep;
+    rec->e_sum = e;
+    rec->energy = -J * (double)e;
+    rec->m_sum = m;
+    if (dense) memset(dense, 0, sizeof(uint64_t) * ((size_t)n + 1u));
+    if (!labels) return;
+    uint32_t *size = (uint32_t *)calloc(n, sizeof(uint32_t));
+    if (!size) return;
+    for (uint32_t s = 0; s < n; ++s) size[labels[s]] += 1u;
+    for (uint32_t r = 0; r < n; ++r) {
+        if (size[r] == 0u) continue;
+        uint64_t sz = size[r];
+        rec->n_clusters += 1u;
+        if (sz > rec->max_cluster) rec->max_cluster = sz;
+        rec->sum_sq_sizes += sz * sz;
+        int k = 0;
+        while ((sz >> (k + 1)) != 0u) ++k;
+        rec->hist_log2[k] += 1u;
+        if (dense) dense[sz] += 1u;
+    }
+    free(size);
+}
+
+/* One full sweep t (Sec. 2, steps 2.1-2.5): bonds, clusters, new spins,
+ * measurement of the new configuration.  `spins` is updated in place;
+ * `labels` (N words) and `bonds` (N bytes) receive the sweep's clusters and
+ * bonds; `rec` the record; `dense` (NULL or N+1 words) the exact cluster
+ * size histogram.  Returns 0, or -1 on allocation failure. */
+int orc_sweep(int32_t L, double J, uint32_t T, uint64_t seed, uint32_t t,
+              int8_t *spins, uint32_t *labels, uint8_t *bonds, orc_obs *rec,
+              uint64_t *dense)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    uint8_t *b = bonds ? bonds : (uint8_t *)malloc(n);
+    uint32_t *lab = labels ? labels : (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!b || !lab) {
+        if (!bonds) free(b);
+        if (!labels) free(lab);
+        return -1;
+    }
+    orc_bonds(L, T, seed, t, spins, b);
+    orc_label(L, b, lab);
+    orc_assign(L, seed, t, lab, spins);
+    if (rec) orc_observe(L, J, t, spins, lab, rec, dense);
+    if (!bonds) free(b);
+    if (!labels) free(lab);
+    return 0;
+}
+
+/* Runs `count` consecutive sweeps t0, t0+1, ... writing one record each. */
+int orc_run(int32_t L, double J, uint32_t T, uint64_t seed, uint32_t t0,
+            int64_t count, int8_t *spins, orc_obs *recs)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    uint8_t *b = (uint8_t *)malloc(n);
+    uint32_t *lab = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!b || !lab) { free(b); free(lab); return -1; }
+    for (int64_t i = 0; i < count; ++i) {
+        uint32_t t = t0 + (uint32_t)i;
+        orc_bonds(L, T, seed, t, spins, b);
+        orc_label(L, b, lab);
+        orc_assign(L, seed, t, lab, spins);
+        if (recs) orc_observe(L, J, t, spins, lab, &recs[i], NULL);
+    }
+    free(b);
+    free(lab);
+    return 0;
+}
+
+/* Ensemble helper for the exact-enumeration pins: runs `nchains`
+ * independent chains (seeds seed0, seed0+1, ...) from a hot start for
+ * `nsweeps` sweeps each and stores the final e_sum and m_sum of each. */
+int orc_chains(int32_t L, double J, uint32_t T, uint64_t seed0, int64_t nchains,
+               int32_t nsweeps, int64_t *e_out, int64_t *m_out)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    int8_t *sp = (int8_t *)malloc(n);
+    if (!sp) return -1;
+    for (int64_t c = 0; c < nchains; ++c) {
+        uint64_t seed = seed0 + (uint64_t)c;
+        orc_init(L, seed, 0, sp);
+        if (orc_run(L, J, T, seed, 0u, nsweeps, sp, NULL) != 0) { free(sp); return -1; }
+        orc_obs rec;
+        orc_observe(L, J, 0, sp, NULL, &rec, NULL);
+        e_out[c] = rec.e_sum;
+        m_out[c] = rec.m_sum;
+    }
+    free(sp);
+    return 0;
+}
+
+/* One sweep from each of `nseeds` seeds, all from the same start state at
+ * sweep index t; stores each resulting configuration as an integer code
+ * (bit s set iff spin s is -1).  For the tiny-torus transition pins. */
+int orc_one_step_codes(int32_t L, uint32_t T, uint64_t seed0, int64_t nseeds,
+                       uint32_t t, const int8_t *start, uint64_t *codes)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    if (n > 64u) return -1;
+    int8_t sp[64];
+    for (int64_t c = 0; c < nseeds; ++c) {
+        memcpy(sp, start, n);
+        if (orc_sweep(L, 1.0, T, seed0 + (uint64_t)c, t, sp, NULL, NULL, NULL, NULL) != 0)
+            return -1;
+        uint64_t code = 0;
+        for (uint32_t s = 0; s < n; ++s)
+            if (sp[s] < 0) code |= (uint64_t)1 << s;
+        codes[c] = code;
+    }
+    return 0;
+}

@@ -1,0 +1,54 @@
+/*
+ * sw_oracle.h -- declarations of the sequential CPU oracle (test
+ * infrastructure only; see sw_oracle.c).  Private to oracle/: the HIP
+ * library neither includes nor links it.
+ */
+#ifndef SW_ORACLE_H
+#define SW_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One record per sweep: observables of the configuration left by the sweep
+ * and statistics of the sweep's clusters. */
+typedef struct {
+    uint64_t sweep;
+    int64_t e_sum;          /* sum over the 2N edges of s_i s_j */
+    double energy;          /* -J * e_sum */
+    int64_t m_sum;          /* sum of s_i */
+    uint64_t n_clusters;
+    uint64_t max_cluster;
+    uint64_t sum_sq_sizes;
+    uint64_t hist_log2[33]; /* clusters with size in [2^k, 2^(k+1)) */
+} orc_obs;
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                       uint32_t out[4]);
+uint32_t orc_threshold(double beta, double J);
+void orc_init(int32_t L, uint64_t seed, int32_t cold, int8_t *spins);
+void orc_bonds(int32_t L, uint32_t T, uint64_t seed, uint32_t t,
+               const int8_t *spins, uint8_t *bonds);
+void orc_label(int32_t L, const uint8_t *bonds, uint32_t *labels);
+int32_t orc_flip_spin(uint64_t seed, uint32_t t, uint32_t root);
+void orc_assign(int32_t L, uint64_t seed, uint32_t t, const uint32_t *labels,
+                int8_t *spins);
+void orc_observe(int32_t L, double J, uint64_t sweep, const int8_t *spins,
+                 const uint32_t *labels, orc_obs *rec, uint64_t *dense);
+int orc_sweep(int32_t L, double J, uint32_t T, uint64_t seed, uint32_t t,
+              int8_t *spins, uint32_t *labels, uint8_t *bonds, orc_obs *rec,
+              uint64_t *dense);
+int orc_run(int32_t L, double J, uint32_t T, uint64_t seed, uint32_t t0,
+            int64_t count, int8_t *spins, orc_obs *recs);
+int orc_chains(int32_t L, double J, uint32_t T, uint64_t seed0, int64_t nchains,
+               int32_t nsweeps, int64_t *e_out, int64_t *m_out);
+int orc_one_step_codes(int32_t L, uint32_t T, uint64_t seed0, int64_t nseeds,
+                       uint32_t t, const int8_t *start, uint64_t *codes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

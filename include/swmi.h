@@ -1,0 +1,182 @@
+/*
+ * swmi.h -- C ABI of libswmi.so: Swendsen-Wang dynamics of the 2D Ising
+ * model on an L x L periodic square lattice, run on one AMD Instinct MI355X
+ * (gfx950) with hand-written HIP kernels.
+ *
+ * The method is the one of Protzman & Giedt, "GPU Acceleration of Swendson-
+ * Wang Dynamics" (Sec. 2): one sweep forms random bonds between equal
+ * neighbouring spins (Sec. 2.1), labels the connected clusters of the bond
+ * graph (Sec. 2.3), gives every cluster a fresh spin, up or down with
+ * probability 1/2 (Sec. 2.4), and measures the new configuration (Sec. 2.5).
+ *
+ * Conventions (shared with the test oracle only by definition, not by code):
+ *   site s = y*L + x (x fastest), periodic; E(s) = y*L + (x+1 mod L),
+ *   N(s) = ((y+1) mod L)*L + x; each site owns its E and N edges.
+ *   Bond threshold T = floor((1 - exp(-2 beta J)) * 2^32), computed once in
+ *   FP64; an edge with equal end spins is bonded iff its uniform 32-bit word
+ *   is below T, so P(bond) = T / 2^32.
+ *   Randomness is Philox4x32-10 keyed by the 64-bit seed:
+ *     edge (s, d), d = 0 (E) / 1 (N), sweep t: word 2*(s&1)+d of the output
+ *       for counter {s>>1, t, 0, 0};
+ *     new spin of the cluster whose smallest site is r, sweep t: bit r mod 128
+ *       of the 128-bit output for counter {r>>7, t, 1, 0} (1 -> -1, 0 -> +1);
+ *     hot start: bit 0 of word 0 for counter {s, 0, 2, 0} (1 -> -1).
+ *   Cluster labels are the smallest site index of the cluster.
+ *   Sweeps are numbered t = 0, 1, ... from create / reset; record t holds the
+ *   statistics of sweep t's clusters and the observables of the configuration
+ *   that sweep t leaves.
+ *
+ * Error behaviour: every int-returning call returns SW_OK (0) or a negative
+ * SW_E* code, and sw_last_error() then describes the failure (thread-local,
+ * valid until the next failing call on the same thread).  No C++ exception
+ * crosses the ABI.  A sim is not thread-safe; distinct sims on distinct
+ * streams may be driven from distinct threads.
+ *
+ * Ownership: an sw_sim owns its device buffers, unless it was created with a
+ * caller workspace (sw_create_in / sw_create_ex), which the caller keeps
+ * alive until sw_destroy.  Host pointers passed in are only read or written
+ * during the call.  All device work runs on the sim's stream, in order.
+ */
+#ifndef SWMI_H
+#define SWMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SW_OK 0
+#define SW_EINVAL (-1)  /* an argument is out of its documented domain      */
+#define SW_ERANGE (-2)  /* an index/length is outside the available range    */
+#define SW_ENOMEM (-3)  /* device or host allocation failed / workspace small */
+#define SW_EHIP (-4)    /* a HIP runtime call failed                          */
+#define SW_ESTATE (-5)  /* the call is not valid in the sim's current state   */
+
+#define SW_INIT_HOT 0   /* i.i.d. +-1 spins drawn from the seed (Fig. 1)     */
+#define SW_INIT_COLD 1  /* all spins +1                                       */
+
+#define SW_FLAG_LABELS 1u      /* keep the canonical labels of the last sweep */
+#define SW_FLAG_DENSE_HIST 2u  /* keep the exact cluster-size histogram       */
+
+typedef struct sw_sim sw_sim;
+
+/* One record per sweep (Sec. 2.5: magnetisation and energy of every new
+ * configuration, plus the statistics of the sweep's clusters).  All sums are
+ * exact integers; energy = -J * e_sum. */
+typedef struct {
+    uint64_t sweep;          /* sweep index t                                  */
+    int64_t e_sum;           /* sum over the 2N torus edges of s_i s_j         */
+    double energy;           /* H = -J sum_<ij> s_i s_j                         */
+    int64_t m_sum;           /* sum of s_i  (M = m_sum / N)                     */
+    uint64_t n_clusters;     /* clusters of sweep t                             */
+    uint64_t max_cluster;    /* largest cluster size                           */
+    uint64_t sum_sq_sizes;   /* sum over clusters of size^2                    */
+    uint64_t hist_log2[33];  /* clusters with size in [2^k, 2^(k+1))           */
+} sw_obs;
+
+/* Creation parameters.  L: lattice side, a multiple of 32 in [32, 32768].
+ * beta >= 0 and J > 0, both finite.  init: SW_INIT_HOT or SW_INIT_COLD.
+ * tile: 0 (automatic: 64 when L is a multiple of 64, else 32), 32 or 64 --
+ * the side of the square tile one workgroup labels in LDS; results do not
+ * depend on it.  flags: SW_FLAG_*.  ring: number of per-sweep records kept
+ * on the device (0 = 4096). */
+typedef struct {
+    int32_t L;
+    int32_t init;
+    int32_t tile;
+    uint32_t flags;
+    double beta;
+    double J;
+    uint64_t seed;
+    int64_t ring;
+} sw_config;
+
+/* Fills *cfg with the given lattice and model and default options
+ * (hot start, automatic tile, no flags, default ring).  SW_EINVAL if cfg is
+ * NULL. */
+int sw_config_init(sw_config *cfg, int32_t L, double beta, double J, uint64_t seed);
+
+/* Device bytes a sim needs for the default options / for *cfg; 0 when the
+ * parameters are invalid.  Use it to size a caller workspace. */
+size_t sw_workspace_bytes(int32_t L);
+size_t sw_workspace_bytes_ex(const sw_config *cfg);
+
+/* Creates a sim (hot start, t = 0) that allocates its own device memory and
+ * its own stream (default priority).  *out receives the handle. */
+int sw_create(int32_t L, double beta, double J, uint64_t seed, sw_sim **out);
+
+/* As sw_create, but carves every device buffer out of the caller's
+ * workspace `dev_workspace` (device pointer, >= sw_workspace_bytes(L) bytes,
+ * 256-byte aligned) and enqueues all work on `hip_stream` (a hipStream_t;
+ * NULL selects the null stream).  SW_ENOMEM if ws_bytes is too small. */
+int sw_create_in(int32_t L, double beta, double J, uint64_t seed,
+                 void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                 sw_sim **out);
+
+/* General form: dev_workspace may be NULL (the library allocates) and
+ * hip_stream may be NULL with dev_workspace NULL (the library creates a
+ * stream). */
+int sw_create_ex(const sw_config *cfg, void *dev_workspace, size_t ws_bytes,
+                 void *hip_stream, sw_sim **out);
+
+/* Re-initialises the spins (SW_INIT_HOT / SW_INIT_COLD) and sets t = 0;
+ * earlier records become unavailable. */
+int sw_reset(sw_sim *sim, int init_mode);
+
+/* Enqueues n >= 0 sweeps on the sim's stream and returns without waiting
+ * (Sec. 2: bonds, clusters, new spins and the record of each sweep). */
+int sw_sweep(sw_sim *sim, int64_t n);
+
+/* Waits for all enqueued work of the sim. */
+int sw_sync(sw_sim *sim);
+
+/* Copies the record of the last completed sweep into *out (waits for the
+ * stream).  SW_ESTATE if no sweep has run since create / reset / set_spins. */
+int sw_observables(sw_sim *sim, sw_obs *out);
+
+/* Copies records of sweeps first .. first+count-1 into out[0..count-1]
+ * (waits).  SW_ERANGE unless all of them ran since the last create / reset /
+ * set_spins and are still held in the ring. */
+int sw_series(sw_sim *sim, int64_t first, int64_t count, sw_obs *out);
+
+/* Exact cluster-size histogram of the last sweep: counts[s] = number of
+ * clusters of size s, s = 0..N (len >= N+1).  Needs SW_FLAG_DENSE_HIST. */
+int sw_cluster_hist(sw_sim *sim, uint64_t *counts, int64_t len);
+
+/* Current spins (int8 +-1, site order s = y*L + x) to host memory;
+ * n must equal N = L*L. */
+int sw_get_spins(sw_sim *sim, int8_t *host, int64_t n);
+
+/* Replaces the spins (each +1 or -1, n == N) and makes next_sweep the index
+ * of the next sweep -- for checkpoint / resume and one-step parity checks.
+ * Records before next_sweep become unavailable. */
+int sw_set_spins(sw_sim *sim, const int8_t *host, int64_t n, uint64_t next_sweep);
+
+/* Canonical labels (smallest site of the cluster) of the last sweep's
+ * clusters to host memory, n == N.  Needs SW_FLAG_LABELS and a completed
+ * sweep. */
+int sw_get_labels(sw_sim *sim, uint32_t *host, int64_t n);
+
+/* The bond threshold T of this sim (so callers can check it). */
+uint32_t sw_threshold(const sw_sim *sim);
+
+/* Index of the next sweep t. */
+int64_t sw_next_sweep(const sw_sim *sim);
+
+/* Lattice side and tile side actually used. */
+int32_t sw_lattice(const sw_sim *sim);
+int32_t sw_tile(const sw_sim *sim);
+
+/* Destroys the sim (waits for its stream first); NULL is a no-op. */
+void sw_destroy(sw_sim *sim);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char *sw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWMI_H */

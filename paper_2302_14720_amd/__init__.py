@@ -1,0 +1,294 @@
+"""Python binding of libswmi.so -- Swendsen-Wang dynamics of the 2D Ising
+model on one MI355X (Protzman & Giedt, Sec. 2).
+
+The binding only marshals arguments: every step of a sweep runs in the HIP
+kernels of ``csrc/``.  Function names match the C ABI in ``include/swmi.h``;
+``Sim`` is a thin object wrapper whose device workspace is a torch uint8
+tensor and whose stream is torch's current stream (torch provides memory and
+streams, nothing else).  If the library has not been built the first call
+raises -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswmi.so")
+
+SW_OK, SW_EINVAL, SW_ERANGE, SW_ENOMEM, SW_EHIP, SW_ESTATE = 0, -1, -2, -3, -4, -5
+SW_INIT_HOT, SW_INIT_COLD = 0, 1
+SW_FLAG_LABELS, SW_FLAG_DENSE_HIST = 1, 2
+
+# Layout of ``sw_obs`` (swmi.h).
+OBS_DTYPE = np.dtype(
+    [
+        ("sweep", "<u8"),
+        ("e_sum", "<i8"),
+        ("energy", "<f8"),
+        ("m_sum", "<i8"),
+        ("n_clusters", "<u8"),
+        ("max_cluster", "<u8"),
+        ("sum_sq_sizes", "<u8"),
+        ("hist_log2", "<u8", (33,)),
+    ]
+)
+assert OBS_DTYPE.itemsize == 320
+
+
+class sw_config(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("init", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("beta", ctypes.c_double),
+        ("J", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("ring", ctypes.c_int64),
+    ]
+
+
+class SwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"swmi error {code}: {msg}")
+        self.code = code
+
+
+# Every symbol swmi.h declares, with (restype, argtypes).
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "sw_config_init": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64]),
+    "sw_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "sw_workspace_bytes_ex": (ctypes.c_size_t, [_P]),
+    "sw_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, _P]),
+    "sw_create_in": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                    _P, ctypes.c_size_t, _P, _P]),
+    "sw_create_ex": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P]),
+    "sw_reset": (ctypes.c_int, [_P, ctypes.c_int]),
+    "sw_sweep": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "sw_sync": (ctypes.c_int, [_P]),
+    "sw_observables": (ctypes.c_int, [_P, _P]),
+    "sw_series": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P]),
+    "sw_cluster_hist": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "sw_get_spins": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "sw_set_spins": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_uint64]),
+    "sw_get_labels": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "sw_threshold": (ctypes.c_uint32, [_P]),
+    "sw_next_sweep": (ctypes.c_int64, [_P]),
+    "sw_lattice": (ctypes.c_int32, [_P]),
+    "sw_tile": (ctypes.c_int32, [_P]),
+    "sw_destroy": (None, [_P]),
+    "sw_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libswmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(l, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = l
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != SW_OK:
+        raise SwError(rc, lib().sw_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ------------------------------------------------------------- C-named calls
+def sw_config_init(L: int, beta: float, J: float = 1.0, seed: int = 0, *, init: int = SW_INIT_HOT,
+                   tile: int = 0, flags: int = 0, ring: int = 0) -> sw_config:
+    cfg = sw_config()
+    _check(lib().sw_config_init(ctypes.byref(cfg), L, beta, J, seed))
+    cfg.init, cfg.tile, cfg.flags, cfg.ring = init, tile, flags, ring
+    return cfg
+
+
+def sw_workspace_bytes(L: int) -> int:
+    return int(lib().sw_workspace_bytes(L))
+
+
+def sw_workspace_bytes_ex(cfg: sw_config) -> int:
+    return int(lib().sw_workspace_bytes_ex(ctypes.byref(cfg)))
+
+
+def sw_create_ex(cfg: sw_config, ws_ptr: int = 0, ws_bytes: int = 0, stream_ptr: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().sw_create_ex(ctypes.byref(cfg), ws_ptr or None, ws_bytes, stream_ptr or None,
+                              ctypes.byref(h)))
+    return h.value
+
+
+def sw_create(L: int, beta: float, J: float, seed: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().sw_create(L, beta, J, seed, ctypes.byref(h)))
+    return h.value
+
+
+def sw_create_in(L: int, beta: float, J: float, seed: int, ws_ptr: int, ws_bytes: int,
+                 stream_ptr: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().sw_create_in(L, beta, J, seed, ws_ptr, ws_bytes, stream_ptr or None, ctypes.byref(h)))
+    return h.value
+
+
+def sw_reset(h: int, init_mode: int = SW_INIT_HOT) -> None:
+    _check(lib().sw_reset(h, init_mode))
+
+
+def sw_sweep(h: int, n: int) -> None:
+    _check(lib().sw_sweep(h, n))
+
+
+def sw_sync(h: int) -> None:
+    _check(lib().sw_sync(h))
+
+
+def sw_observables(h: int) -> np.void:
+    out = np.zeros(1, dtype=OBS_DTYPE)
+    _check(lib().sw_observables(h, _ptr(out)))
+    return out[0]
+
+
+def sw_series(h: int, first: int, count: int) -> np.ndarray:
+    out = np.zeros(count, dtype=OBS_DTYPE)
+    _check(lib().sw_series(h, first, count, _ptr(out)))
+    return out
+
+
+def sw_cluster_hist(h: int, n_sites: int) -> np.ndarray:
+    out = np.zeros(n_sites + 1, dtype=np.uint64)
+    _check(lib().sw_cluster_hist(h, _ptr(out), out.size))
+    return out
+
+
+def sw_get_spins(h: int, n_sites: int) -> np.ndarray:
+    out = np.empty(n_sites, dtype=np.int8)
+    _check(lib().sw_get_spins(h, _ptr(out), n_sites))
+    return out
+
+
+def sw_set_spins(h: int, spins: np.ndarray, next_sweep: int) -> None:
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    _check(lib().sw_set_spins(h, _ptr(s), s.size, next_sweep))
+
+
+def sw_get_labels(h: int, n_sites: int) -> np.ndarray:
+    out = np.empty(n_sites, dtype=np.uint32)
+    _check(lib().sw_get_labels(h, _ptr(out), n_sites))
+    return out
+
+
+def sw_threshold(h: int) -> int:
+    return int(lib().sw_threshold(h))
+
+
+def sw_next_sweep(h: int) -> int:
+    return int(lib().sw_next_sweep(h))
+
+
+def sw_destroy(h: int) -> None:
+    if h:
+        lib().sw_destroy(h)
+
+
+def sw_last_error() -> str:
+    return lib().sw_last_error().decode()
+
+
+# ------------------------------------------------------------------- wrapper
+class Sim:
+    """One lattice on the current GPU; workspace and stream come from torch."""
+
+    def __init__(self, L: int, beta: float, J: float = 1.0, seed: int = 0, *, init: int = SW_INIT_HOT,
+                 tile: int = 0, flags: int = 0, ring: int = 0, device=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("Sim needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.L, self.N = L, L * L
+        self.cfg = sw_config_init(L, beta, J, seed, init=init, tile=tile, flags=flags, ring=ring)
+        nbytes = sw_workspace_bytes_ex(self.cfg)
+        if nbytes == 0:
+            # same validation as create, for the error message
+            self.handle = sw_create_ex(self.cfg)
+        dev = torch.device("cuda" if device is None else device)
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        # a stream of our own (default priority): the legacy null stream
+        # cannot be captured into a graph
+        self._stream = torch.cuda.Stream(device=dev)
+        torch.cuda.current_stream(dev).synchronize()
+        self.handle = sw_create_ex(self.cfg, self._ws.data_ptr(), nbytes, self._stream.cuda_stream)
+
+    def sweep(self, n: int) -> None:
+        sw_sweep(self.handle, n)
+
+    def sync(self) -> None:
+        sw_sync(self.handle)
+
+    def reset(self, init: int = SW_INIT_HOT) -> None:
+        sw_reset(self.handle, init)
+
+    def observables(self):
+        return sw_observables(self.handle)
+
+    def series(self, first: int, count: int) -> np.ndarray:
+        return sw_series(self.handle, first, count)
+
+    def spins(self) -> np.ndarray:
+        return sw_get_spins(self.handle, self.N)
+
+    def set_spins(self, spins: np.ndarray, next_sweep: int) -> None:
+        sw_set_spins(self.handle, spins, next_sweep)
+
+    def labels(self) -> np.ndarray:
+        return sw_get_labels(self.handle, self.N)
+
+    def cluster_hist(self) -> np.ndarray:
+        return sw_cluster_hist(self.handle, self.N)
+
+    @property
+    def threshold(self) -> int:
+        return sw_threshold(self.handle)
+
+    @property
+    def next_sweep(self) -> int:
+        return sw_next_sweep(self.handle)
+
+    @property
+    def tile(self) -> int:
+        return int(lib().sw_tile(self.handle))
+
+    def close(self) -> None:
+        h, self.handle = getattr(self, "handle", None), None
+        if h:
+            sw_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,460 @@
+// sw_api.hip -- host runtime and C ABI of libswmi (declared in swmi.h).
+//
+// A sim owns (or borrows) one device workspace carved into the buffers of
+// sw_internal.h, one stream, and one captured hipGraph holding the kernels
+// of a single sweep; sw_sweep(n) replays that graph n times and ends with
+// k_resolve, so between calls the spin buffer always holds final +-1 spins.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sw_internal.h"
+
+using swmi::Dev;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(SW_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                     \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kDefaultRing = 4096;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Bond probability p = 1 - exp(-2 beta J) (Sec. 2.1, read with the factor 2J
+// that puts T_c at 2/ln(1+sqrt 2)), as a 32-bit threshold: P(bond) = T/2^32.
+uint32_t bond_threshold(double beta, double J) {
+    const double p = -expm1(-2.0 * beta * J);
+    if (!(p > 0.0)) return 0u;
+    const double scaled = floor(ldexp(p, 32));
+    if (scaled >= 4294967296.0) return 0xFFFFFFFFu;
+    return (uint32_t)scaled;
+}
+
+struct Layout {
+    size_t spins[2], parent[2], nk[2], key, nsize, rspin, edge, xb, tpart, gpart, acc, tdev, ring, labels,
+        dense, total;
+};
+
+int resolve_tile(const sw_config &c) {
+    if (c.tile == 0) return (c.L % 64 == 0) ? 64 : 32;
+    return c.tile;
+}
+
+int validate(const sw_config *c) {
+    if (!c) return fail(SW_EINVAL, "config is NULL");
+    if (c->L < 32 || c->L > 32768 || c->L % 32 != 0)
+        return fail(SW_EINVAL, "L must be a multiple of 32 in [32, 32768]");
+    if (!(c->beta >= 0.0) || !isfinite(c->beta)) return fail(SW_EINVAL, "beta must be finite and >= 0");
+    if (!(c->J > 0.0) || !isfinite(c->J)) return fail(SW_EINVAL, "J must be finite and > 0");
+    if (c->init != SW_INIT_HOT && c->init != SW_INIT_COLD) return fail(SW_EINVAL, "init must be SW_INIT_HOT or SW_INIT_COLD");
+    if (c->tile != 0 && c->tile != 32 && c->tile != 64) return fail(SW_EINVAL, "tile must be 0, 32 or 64");
+    if (c->tile == 64 && c->L % 64 != 0) return fail(SW_EINVAL, "tile 64 needs L to be a multiple of 64");
+    if ((c->flags & ~(SW_FLAG_LABELS | SW_FLAG_DENSE_HIST)) != 0u) return fail(SW_EINVAL, "unknown flag bits");
+    if (c->ring < 0 || c->ring > (int64_t)1 << 30) return fail(SW_EINVAL, "ring must be in [0, 2^30]");
+    return SW_OK;
+}
+
+Layout layout_of(const sw_config &c) {
+    const size_t L = (size_t)c.L, N = L * L;
+    const size_t tw = (size_t)resolve_tile(c);
+    const size_t ntiles = (L / tw) * (L / tw);
+    const size_t ngroups = (ntiles + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
+    const size_t nodes = ntiles * swmi::kNodeSlots;
+    const size_t ring = (size_t)(c.ring > 0 ? c.ring : kDefaultRing);
+    Layout o{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    o.spins[0] = take(N);
+    o.spins[1] = take(N);
+    o.parent[0] = take(nodes * 4);
+    o.parent[1] = take(nodes * 4);
+    o.nk[0] = take(ntiles * 4);
+    o.nk[1] = take(ntiles * 4);
+    o.key = take(nodes * 4);
+    o.nsize = take(nodes * 4);
+    o.rspin = take(nodes);
+    o.edge = take(ntiles * 4 * tw);
+    o.xb = take(ntiles * 16);
+    o.tpart = take(ntiles * swmi::kTilePart * 4);
+    o.gpart = take(ngroups * swmi::kGroupPart * 8);
+    o.acc = take(swmi::kAccWords * 8);
+    o.tdev = take(8);
+    o.ring = take(ring * sizeof(sw_obs));
+    o.labels = (c.flags & SW_FLAG_LABELS) ? take(N * 4) : 0;
+    o.dense = (c.flags & SW_FLAG_DENSE_HIST) ? take((N + 1) * 8) : 0;
+    o.total = off;
+    return o;
+}
+
+}  // namespace
+
+struct sw_sim {
+    sw_config cfg;
+    Dev dev;
+    hipStream_t stream;
+    bool own_stream;
+    void *ws;
+    size_t ws_bytes;
+    bool own_ws;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    bool graph_tried;
+    uint64_t next_sweep;   // host mirror of *dev.tdev
+    uint64_t first_valid;  // first sweep whose record exists
+    int device;
+};
+
+namespace {
+
+int ensure_device(const sw_sim *s) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != s->device) HIP_TRY(hipSetDevice(s->device));
+    return SW_OK;
+}
+
+int set_tdev(sw_sim *s, uint64_t t) {
+    HIP_TRY(hipMemcpyAsync(s->dev.tdev, &t, sizeof(t), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->next_sweep = t;
+    s->first_valid = t;
+    return SW_OK;
+}
+
+void drop_graph(sw_sim *s) {
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+    s->graph_tried = false;
+}
+
+// Captures one sweep into a graph (not on the legacy null stream, which
+// cannot be captured); on any capture failure the sweeps are launched
+// directly, with the same kernels.
+void ensure_graph(sw_sim *s) {
+    if (s->graph_tried) return;
+    s->graph_tried = true;
+    if (s->stream == nullptr) return;
+    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    const hipError_t le = swmi::launch_sweep(s->dev, s->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(s->stream, &g);
+    if (le != hipSuccess || ce != hipSuccess || g == nullptr) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return;
+    }
+    hipGraphExec_t ge = nullptr;
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return;
+    }
+    s->graph = g;
+    s->gexec = ge;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sw_last_error(void) { return g_err.c_str(); }
+
+int sw_config_init(sw_config *cfg, int32_t L, double beta, double J, uint64_t seed) {
+    if (!cfg) return fail(SW_EINVAL, "cfg is NULL");
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->L = L;
+    cfg->beta = beta;
+    cfg->J = J;
+    cfg->seed = seed;
+    cfg->init = SW_INIT_HOT;
+    cfg->tile = 0;
+    cfg->flags = 0u;
+    cfg->ring = 0;
+    return SW_OK;
+}
+
+size_t sw_workspace_bytes_ex(const sw_config *cfg) {
+    if (validate(cfg) != SW_OK) return 0;
+    return layout_of(*cfg).total;
+}
+
+size_t sw_workspace_bytes(int32_t L) {
+    sw_config c;
+    sw_config_init(&c, L, 0.0, 1.0, 0);
+    return sw_workspace_bytes_ex(&c);
+}
+
+int sw_create_ex(const sw_config *cfg, void *dev_workspace, size_t ws_bytes, void *hip_stream, sw_sim **out) {
+    if (!out) return fail(SW_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc != SW_OK) return rc;
+    const Layout lo = layout_of(*cfg);
+    if (dev_workspace && ws_bytes < lo.total)
+        return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(lo.total) + " bytes");
+    if (dev_workspace && ((uintptr_t)dev_workspace % kAlign) != 0)
+        return fail(SW_EINVAL, "workspace must be 256-byte aligned");
+
+    sw_sim *s = new (std::nothrow) sw_sim();
+    if (!s) return fail(SW_ENOMEM, "host allocation failed");
+    s->cfg = *cfg;
+    if (s->cfg.ring == 0) s->cfg.ring = kDefaultRing;
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "hipGetDevice");
+    }
+    if (dev_workspace) {
+        s->ws = dev_workspace;
+        s->ws_bytes = ws_bytes;
+        s->own_ws = false;
+        s->stream = (hipStream_t)hip_stream;
+        s->own_stream = false;
+    } else {
+        e = hipMalloc(&s->ws, lo.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return fail(SW_ENOMEM, "hipMalloc of " + std::to_string(lo.total) + " bytes failed");
+        }
+        s->ws_bytes = lo.total;
+        s->own_ws = true;
+        if (hip_stream) {
+            s->stream = (hipStream_t)hip_stream;
+            s->own_stream = false;
+        } else {
+            e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                (void)hipFree(s->ws);
+                delete s;
+                return hip_fail(e, "hipStreamCreateWithFlags");
+            }
+            s->own_stream = true;
+        }
+    }
+    char *base = (char *)s->ws;
+    const sw_config &c = s->cfg;
+    Dev &d = s->dev;
+    memset(&d, 0, sizeof(d));
+    d.L = (uint32_t)c.L;
+    d.tw = (uint32_t)resolve_tile(c);
+    d.ntx = d.L / d.tw;
+    d.ntiles = d.ntx * d.ntx;
+    d.ngroups = (d.ntiles + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
+    d.T = bond_threshold(c.beta, c.J);
+    d.seed_lo = (uint32_t)(c.seed & 0xFFFFFFFFu);
+    d.seed_hi = (uint32_t)(c.seed >> 32);
+    d.ring_cap = (uint32_t)c.ring;
+    d.J = c.J;
+    for (int i = 0; i < 2; ++i) {
+        d.spins[i] = (int8_t *)(base + lo.spins[i]);
+        d.parent[i] = (uint32_t *)(base + lo.parent[i]);
+        d.nk[i] = (uint32_t *)(base + lo.nk[i]);
+    }
+    d.key = (uint32_t *)(base + lo.key);
+    d.nsize = (uint32_t *)(base + lo.nsize);
+    d.rspin = (int8_t *)(base + lo.rspin);
+    d.edge = (uint8_t *)(base + lo.edge);
+    d.xb = (uint64_t *)(base + lo.xb);
+    d.tpart = (int32_t *)(base + lo.tpart);
+    d.gpart = (uint64_t *)(base + lo.gpart);
+    d.acc = (uint64_t *)(base + lo.acc);
+    d.tdev = (uint64_t *)(base + lo.tdev);
+    d.ring = (sw_obs *)(base + lo.ring);
+    d.labels = (c.flags & SW_FLAG_LABELS) ? (uint32_t *)(base + lo.labels) : nullptr;
+    d.dense = (c.flags & SW_FLAG_DENSE_HIST) ? (uint64_t *)(base + lo.dense) : nullptr;
+
+    // Everything starts at zero: no nodes in either parity, empty accumulators.
+    e = hipMemsetAsync(s->ws, 0, lo.total, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "clearing the workspace");
+        sw_destroy(s);
+        return rc;
+    }
+    rc = sw_reset(s, c.init);
+    if (rc != SW_OK) {
+        const std::string msg = g_err;
+        sw_destroy(s);
+        return fail(rc, msg);
+    }
+    *out = s;
+    return SW_OK;
+}
+
+int sw_create_in(int32_t L, double beta, double J, uint64_t seed, void *dev_workspace, size_t ws_bytes,
+                 void *hip_stream, sw_sim **out) {
+    if (!dev_workspace) return fail(SW_EINVAL, "dev_workspace is NULL");
+    sw_config c;
+    sw_config_init(&c, L, beta, J, seed);
+    return sw_create_ex(&c, dev_workspace, ws_bytes, hip_stream, out);
+}
+
+int sw_create(int32_t L, double beta, double J, uint64_t seed, sw_sim **out) {
+    sw_config c;
+    sw_config_init(&c, L, beta, J, seed);
+    return sw_create_ex(&c, nullptr, 0, nullptr, out);
+}
+
+int sw_reset(sw_sim *s, int init_mode) {
+    if (!s) return fail(SW_EINVAL, "sim is NULL");
+    if (init_mode != SW_INIT_HOT && init_mode != SW_INIT_COLD)
+        return fail(SW_EINVAL, "init_mode must be SW_INIT_HOT or SW_INIT_COLD");
+    int rc = ensure_device(s);
+    if (rc != SW_OK) return rc;
+    rc = set_tdev(s, 0);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(swmi::launch_init(s->dev, init_mode == SW_INIT_COLD ? 1 : 0, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SW_OK;
+}
+
+int sw_sweep(sw_sim *s, int64_t n) {
+    if (!s) return fail(SW_EINVAL, "sim is NULL");
+    if (n < 0) return fail(SW_EINVAL, "n must be >= 0");
+    if (n == 0) return SW_OK;
+    int rc = ensure_device(s);
+    if (rc != SW_OK) return rc;
+    ensure_graph(s);
+    for (int64_t i = 0; i < n; ++i) {
+        if (s->gexec)
+            HIP_TRY(hipGraphLaunch(s->gexec, s->stream));
+        else
+            HIP_TRY(swmi::launch_sweep(s->dev, s->stream));
+    }
+    HIP_TRY(swmi::launch_resolve(s->dev, s->stream));
+    s->next_sweep += (uint64_t)n;
+    return SW_OK;
+}
+
+int sw_sync(sw_sim *s) {
+    if (!s) return fail(SW_EINVAL, "sim is NULL");
+    int rc = ensure_device(s);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SW_OK;
+}
+
+int sw_series(sw_sim *s, int64_t first, int64_t count, sw_obs *out) {
+    if (!s) return fail(SW_EINVAL, "sim is NULL");
+    if (count < 0 || (count > 0 && !out)) return fail(SW_EINVAL, "bad count or NULL out");
+    if (count == 0) return SW_OK;
+    if (first < (int64_t)s->first_valid || first + count > (int64_t)s->next_sweep)
+        return fail(SW_ERANGE, "records requested outside the sweeps run since the last reset / set_spins");
+    const uint64_t cap = s->dev.ring_cap;
+    if ((uint64_t)(s->next_sweep - (uint64_t)first) > cap)
+        return fail(SW_ERANGE, "records requested have left the ring");
+    int rc = ensure_device(s);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    int64_t done = 0;
+    while (done < count) {
+        const uint64_t idx = (uint64_t)(first + done) % cap;
+        const int64_t chunk = (int64_t)std::min<uint64_t>((uint64_t)(count - done), cap - idx);
+        HIP_TRY(hipMemcpyAsync(out + done, s->dev.ring + idx, (size_t)chunk * sizeof(sw_obs), hipMemcpyDeviceToHost,
+                               s->stream));
+        done += chunk;
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SW_OK;
+}
+
+int sw_observables(sw_sim *s, sw_obs *out) {
+    if (!s || !out) return fail(SW_EINVAL, "sim or out is NULL");
+    if (s->next_sweep == s->first_valid) return fail(SW_ESTATE, "no sweep has run since the last reset / set_spins");
+    return sw_series(s, (int64_t)s->next_sweep - 1, 1, out);
+}
+
+int sw_cluster_hist(sw_sim *s, uint64_t *counts, int64_t len) {
+    if (!s || !counts) return fail(SW_EINVAL, "sim or counts is NULL");
+    if (!s->dev.dense) return fail(SW_ESTATE, "sim was created without SW_FLAG_DENSE_HIST");
+    const int64_t n = (int64_t)s->dev.L * s->dev.L;
+    if (len < n + 1) return fail(SW_ERANGE, "len must be >= N + 1");
+    if (s->next_sweep == s->first_valid) return fail(SW_ESTATE, "no sweep has run since the last reset / set_spins");
+    int rc = ensure_device(s);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(counts, s->dev.dense, (size_t)(n + 1) * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SW_OK;
+}
+
+int sw_get_spins(sw_sim *s, int8_t *host, int64_t n) {
+    if (!s || !host) return fail(SW_EINVAL, "sim or host is NULL");
+    if (n != (int64_t)s->dev.L * s->dev.L) return fail(SW_ERANGE, "n must equal L*L");
+    int rc = ensure_device(s);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(host, s->dev.spins[s->next_sweep & 1u], (size_t)n, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SW_OK;
+}
+
+int sw_set_spins(sw_sim *s, const int8_t *host, int64_t n, uint64_t next_sweep) {
+    if (!s || !host) return fail(SW_EINVAL, "sim or host is NULL");
+    if (n != (int64_t)s->dev.L * s->dev.L) return fail(SW_ERANGE, "n must equal L*L");
+    for (int64_t i = 0; i < n; ++i)
+        if (host[i] != 1 && host[i] != -1) return fail(SW_EINVAL, "spins must be +1 or -1");
+    int rc = ensure_device(s);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpyAsync(s->dev.spins[next_sweep & 1u], host, (size_t)n, hipMemcpyHostToDevice, s->stream));
+    return set_tdev(s, next_sweep);
+}
+
+int sw_get_labels(sw_sim *s, uint32_t *host, int64_t n) {
+    if (!s || !host) return fail(SW_EINVAL, "sim or host is NULL");
+    if (!s->dev.labels) return fail(SW_ESTATE, "sim was created without SW_FLAG_LABELS");
+    if (n != (int64_t)s->dev.L * s->dev.L) return fail(SW_ERANGE, "n must equal L*L");
+    if (s->next_sweep == s->first_valid) return fail(SW_ESTATE, "no sweep has run since the last reset / set_spins");
+    int rc = ensure_device(s);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(host, s->dev.labels, (size_t)n * 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SW_OK;
+}
+
+uint32_t sw_threshold(const sw_sim *s) { return s ? s->dev.T : 0u; }
+int64_t sw_next_sweep(const sw_sim *s) { return s ? (int64_t)s->next_sweep : -1; }
+int32_t sw_lattice(const sw_sim *s) { return s ? (int32_t)s->dev.L : 0; }
+int32_t sw_tile(const sw_sim *s) { return s ? (int32_t)s->dev.tw : 0; }
+
+void sw_destroy(sw_sim *s) {
+    if (!s) return;
+    (void)ensure_device(s);
+    (void)hipStreamSynchronize(s->stream);
+    drop_graph(s);
+    if (s->own_ws && s->ws) (void)hipFree(s->ws);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+}  // extern "C"

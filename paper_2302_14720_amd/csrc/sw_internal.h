@@ -1,0 +1,67 @@
+// sw_internal.h -- device-state layout and kernel entry points of libswmi.
+//
+// One sweep (paper Sec. 2) runs as five kernels on the sim's stream:
+//   k_tile    bond formation (Sec. 2.1) and cluster formation (Sec. 2.3)
+//             inside one 64x64 (or 32x32) tile per workgroup, in LDS; new
+//             spins (Sec. 2.4) of clusters that stay inside the tile; the
+//             tile's boundary clusters become "nodes" of a global graph;
+//             the spins of the previous sweep are resolved on the fly and
+//             measured (Sec. 2.5).
+//   k_union   union of nodes joined by bonds that cross tile edges, by
+//             lock-free union-find in global memory (lowest site wins).
+//   k_flatten point every node at its root; add node sizes into the roots.
+//   k_roots   new spin of each cross-tile cluster, cluster statistics.
+//   k_record  fold partial statistics into the per-sweep record ring.
+// Spins are double-buffered by sweep parity.  A written spin byte is either
+// the final spin (0x01 = +1, 0xFF = -1) or 2 + k, a reference to node k of
+// the tile, resolved through the node tables of that sweep when the byte is
+// read next (by the next sweep's k_tile, or by k_resolve at the end of
+// every sw_sweep call).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "swmi.h"
+
+namespace swmi {
+
+constexpr uint32_t kNodeSlots = 256;  // node slots per tile (64x64 tile: <= 252 nodes)
+constexpr int kTilePart = 32;         // int32 words of a per-tile partial
+constexpr int kGroupPart = 40;        // uint64 words of a per-group partial
+constexpr int kAccWords = 64;         // record accumulator + completion counter
+constexpr int kGroupTiles = 16;       // tiles per workgroup in k_flatten / k_roots
+
+// tile partial (int32 words)
+enum { TP_E = 0, TP_M = 1, TP_N = 2, TP_MAX = 3, TP_SQ = 4, TP_HIST = 5 };  // hist: 12 bins
+// group partial / accumulator (uint64 words)
+enum { GP_N = 0, GP_MAX = 1, GP_SQ = 2, GP_E = 3, GP_M = 4, GP_HIST = 5, GP_END = 38 };
+enum { ACC_COUNT = 48 };
+
+struct Dev {
+    int8_t *spins[2];     // [N] by sweep parity
+    uint32_t *parent[2];  // [ntiles * kNodeSlots] by sweep parity
+    uint32_t *nk[2];      // [ntiles] number of nodes per tile, by parity
+    uint32_t *key;        // [ntiles * kNodeSlots] smallest site of the node
+    uint32_t *nsize;      // [ntiles * kNodeSlots] node size; cluster size at roots
+    int8_t *rspin;        // [ntiles * kNodeSlots] new spin, valid at root nodes
+    uint8_t *edge;        // [ntiles][4][tw] node index of W, E, S, N edge sites
+    uint64_t *xb;         // [ntiles][2] bonds leaving the tile: E (bit y), N (bit x)
+    int32_t *tpart;       // [ntiles][kTilePart]
+    uint64_t *gpart;      // [ngroups][kGroupPart]
+    uint64_t *acc;        // [kAccWords]
+    uint64_t *tdev;       // [0] = index of the next sweep
+    sw_obs *ring;         // [ring_cap]
+    uint32_t *labels;     // [N] or nullptr
+    uint64_t *dense;      // [N + 1] or nullptr
+    uint32_t L, tw, ntx, ntiles, ngroups;
+    uint32_t T, seed_lo, seed_hi;
+    uint32_t ring_cap;
+    double J;
+};
+
+hipError_t launch_init(const Dev &d, int cold, hipStream_t s);
+hipError_t launch_sweep(const Dev &d, hipStream_t s);
+hipError_t launch_resolve(const Dev &d, hipStream_t s);
+
+}  // namespace swmi

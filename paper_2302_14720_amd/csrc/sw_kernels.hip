@@ -1,0 +1,970 @@
+// sw_kernels.hip -- gfx950 kernels of one Swendsen-Wang sweep (see
+// sw_internal.h for the pipeline).  Written for 64-wide wavefronts: a tile
+// row of 64 sites is one 64-bit mask, so row runs of horizontal bonds come
+// from bit arithmetic on ballot-sized masks, and only vertical bonds go
+// through the LDS union-find.
+#include "sw_internal.h"
+
+namespace swmi {
+namespace {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// products; the key advances by the Weyl constants between rounds.
+__device__ __forceinline__ void philox10(uint32_t &x0, uint32_t &x1, uint32_t &x2,
+                                         uint32_t &x3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)0xD2511F53u * x0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ x1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)pb;
+        x3 = (uint32_t)pa;
+        x0 = n0;
+        x2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// New spin (+1 / -1) of the cluster whose smallest site is r in sweep t:
+// bit r mod 128 of the 128-bit output for counter {r >> 7, t, 1, 0}.
+__device__ __forceinline__ int8_t cluster_spin(uint32_t r, uint32_t t, uint32_t k0, uint32_t k1) {
+    uint32_t w0 = r >> 7, w1 = t, w2 = 1u, w3 = 0u;
+    philox10(w0, w1, w2, w3, k0, k1);
+    const uint32_t q = (r >> 5) & 3u;
+    const uint32_t w = q == 0 ? w0 : q == 1 ? w1 : q == 2 ? w2 : w3;
+    return ((w >> (r & 31u)) & 1u) ? (int8_t)-1 : (int8_t)1;
+}
+
+template <int TW> struct RowOf;
+template <> struct RowOf<64> { using T = uint64_t; };
+template <> struct RowOf<32> { using T = uint32_t; };
+
+// Highest set bit of B at a position <= x (bit 0 of B is always set).
+__device__ __forceinline__ uint32_t hsb_le(uint64_t B, uint32_t x) {
+    const uint64_t m = B & (~0ull >> (63u - x));
+    return 63u - (uint32_t)__clzll((long long)m);
+}
+__device__ __forceinline__ uint32_t hsb_le(uint32_t B, uint32_t x) {
+    const uint32_t m = B & (~0u >> (31u - x));
+    return 31u - (uint32_t)__clz((int)m);
+}
+
+// Workgroup b runs on XCD b % 8; give each XCD a contiguous band of tiles so
+// that neighbouring tiles (which share halo rows and cache lines) meet in
+// the same L2.
+__device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t n) {
+    if ((n & 7u) == 0u) return (b & 7u) * (n >> 3) + (b >> 3);
+    return b;
+}
+
+// ---------------------------------------------------------------- LDS union-find
+__device__ __forceinline__ uint32_t lds_load(uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Roots are the smallest index of their set and every parent is smaller
+// than its child.  Path halving lowers entries with atomicMin: a plain store
+// could overwrite a fully compressed entry (the root) with a larger ancestor
+// read earlier by another thread, whereas with min-updates every entry only
+// ever decreases towards its root.
+__device__ __forceinline__ uint32_t lds_find(uint32_t *par, uint32_t a) {
+    while (true) {
+        const uint32_t p = lds_load(&par[a]);
+        if (p == a) return a;
+        const uint32_t gp = lds_load(&par[p]);
+        if (gp == p) return p;
+        atomicMin(&par[a], gp);
+        a = gp;
+    }
+}
+__device__ __forceinline__ void lds_union(uint32_t *par, uint32_t a, uint32_t b) {
+    while (true) {
+        a = lds_find(par, a);
+        b = lds_find(par, b);
+        if (a == b) return;
+        if (a > b) { const uint32_t tmp = a; a = b; b = tmp; }
+        uint32_t expected = b;
+        if (__hip_atomic_compare_exchange_strong(&par[b], &expected, a, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+    }
+}
+
+// ---------------------------------------------------------- global union-find
+// Nodes are ordered by key (their smallest site); a root is linked under the
+// root with the smaller key, so the final root of a cluster holds the
+// cluster's smallest site whatever order the unions run in.
+__device__ __forceinline__ uint32_t g_load(uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_store(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t g_find(uint32_t *par, uint32_t a) {
+    while (true) {
+        const uint32_t p = g_load(&par[a]);
+        if (p == a) return a;
+        const uint32_t gp = g_load(&par[p]);
+        if (gp == p) return p;
+        g_store(&par[a], gp);
+        a = gp;
+    }
+}
+// Root of a without writing anything: used once the unions are complete, so
+// that every store that follows is a root (a halving store racing with them
+// could leave a non-root ancestor behind).
+__device__ __forceinline__ uint32_t g_root(const uint32_t *par, uint32_t a) {
+    while (true) {
+        const uint32_t p = __hip_atomic_load(&par[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == a) return a;
+        a = p;
+    }
+}
+__device__ __forceinline__ void g_union(uint32_t *par, const uint32_t *key, uint32_t a, uint32_t b) {
+    while (true) {
+        a = g_find(par, a);
+        b = g_find(par, b);
+        if (a == b) return;
+        if (key[a] > key[b]) { const uint32_t tmp = a; a = b; b = tmp; }
+        uint32_t expected = b;
+        if (__hip_atomic_compare_exchange_strong(&par[b], &expected, a, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return;
+    }
+}
+
+// Spin (+1/-1) encoded by a byte of the previous sweep's output that belongs
+// to tile `tile`: final spins are 0x01 / 0xFF, a code 2 + k refers to node k
+// of that tile, whose root's spin was fixed by k_roots.
+__device__ __forceinline__ int8_t resolve_byte(uint32_t b, uint32_t tile, const uint32_t *par_prev,
+                                               const int8_t *rspin, uint32_t nnodes) {
+    const uint32_t k = b - 2u;
+    if (k < 252u) {
+        uint32_t p = par_prev[tile * kNodeSlots + k];
+        p = p < nnodes ? p : 0u;
+        return rspin[p];
+    }
+    return (int8_t)b;
+}
+
+__device__ __forceinline__ uint32_t byte_at(const uint4 &v, int q) {
+    const uint32_t w = q < 4 ? v.x : q < 8 ? v.y : q < 12 ? v.z : v.w;
+    return (w >> (8 * (q & 3))) & 0xFFu;
+}
+
+// Shared front end of k_tile and k_resolve: load the tile's spin bytes and
+// its E / N halo, decode them to up-spin bit masks.
+template <int TW>
+struct TileFront {
+    using Row = typename RowOf<TW>::T;
+    static constexpr int NT = TW * TW / 16;
+    static constexpr int RPT = TW / 16;
+};
+
+template <int TW>
+__device__ __forceinline__ void load_table(const Dev &d, uint32_t tile, uint32_t pp, int8_t *s_tab,
+                                           uint32_t tid) {
+    constexpr int NT = TW * TW / 16;
+    const uint32_t nnodes = d.ntiles * kNodeSlots;
+    const uint32_t kprev = min(d.nk[pp][tile], 252u);
+    const uint32_t *par_prev = d.parent[pp];
+    for (uint32_t b = tid; b < 256u; b += NT) {
+        int8_t val = (b == 0xFFu) ? (int8_t)-1 : (int8_t)1;
+        const uint32_t k = b - 2u;
+        if (k < kprev) {
+            uint32_t p = par_prev[tile * kNodeSlots + k];
+            p = p < nnodes ? p : 0u;
+            val = d.rspin[p];
+        }
+        s_tab[b] = val;
+    }
+}
+
+template <int TW>
+__device__ __forceinline__ uint32_t decode16(const uint4 &v, const int8_t *s_tab) {
+    uint32_t up = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) up |= (uint32_t)(s_tab[byte_at(v, q)] > 0) << q;
+    return up;
+}
+
+__device__ __forceinline__ uint32_t decode16_remote(const uint4 &v, uint32_t tile, const uint32_t *par_prev,
+                                                    const int8_t *rspin, uint32_t nnodes) {
+    uint32_t up = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        up |= (uint32_t)(resolve_byte(byte_at(v, q), tile, par_prev, rspin, nnodes) > 0) << q;
+    return up;
+}
+
+// =====================================================================
+// k_tile: bonds (Sec. 2.1), tile-local clusters (Sec. 2.3), new spins of
+// tile-interior clusters (Sec. 2.4), measurement of the incoming
+// configuration (Sec. 2.5).  One workgroup per TW x TW tile, 16 sites per
+// thread (one 16-site segment of a row).
+// =====================================================================
+template <int TW>
+__global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
+    using Row = typename RowOf<TW>::T;
+    constexpr int NT = TW * TW / 16;
+    constexpr uint32_t RPT = TW / 16;
+    constexpr int NS = TW * TW;
+    constexpr int NW = NS / 32;
+    constexpr int NWAVE = (NT + 63) / 64;
+
+    __shared__ Row s_up[TW + 1];
+    __shared__ Row s_eb[TW];
+    __shared__ Row s_nb[TW];
+    __shared__ Row s_fb[TW];
+    __shared__ Row s_xn;
+    __shared__ uint32_t s_eup[(TW + 31) / 32];
+    __shared__ uint32_t s_xe[(TW + 31) / 32];
+    __shared__ uint32_t s_par[NS];
+    __shared__ uint32_t s_sz[NS / 2];
+    __shared__ uint32_t s_bf[NW];
+    __shared__ uint32_t s_pf[NW];
+    __shared__ int8_t s_tab[256];
+    __shared__ uint32_t s_hist[12];
+    __shared__ int32_t s_red[NWAVE][5];
+    __shared__ uint32_t s_k;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t L = d.L, ntx = d.ntx;
+    const uint32_t tile = tile_of_block(blockIdx.x, d.ntiles);
+    const uint32_t tx = tile % ntx, ty = tile / ntx;
+    const uint64_t tsw = *d.tdev;
+    const uint32_t t = (uint32_t)tsw;
+    const uint32_t pc = (uint32_t)(tsw & 1u), pp = pc ^ 1u;
+    const int8_t *__restrict__ sin = d.spins[pc];
+    int8_t *__restrict__ sout = d.spins[pp];
+    const uint32_t *__restrict__ par_prev = d.parent[pp];
+    uint32_t *__restrict__ par_cur = d.parent[pc];
+    const uint32_t nnodes = d.ntiles * kNodeSlots;
+
+    const uint32_t ly = tid / RPT, seg = tid % RPT, x0 = seg * 16u;
+    const uint32_t gy = ty * TW + ly, gx0 = tx * TW + x0;
+    const uint32_t east = ty * ntx + (tx + 1u == ntx ? 0u : tx + 1u);
+    const uint32_t north = (ty + 1u == ntx ? 0u : ty + 1u) * ntx + tx;
+    const uint32_t rowbase = ly * TW;
+
+    // ---- issue the spin loads first, then build the node table
+    const uint4 v = *reinterpret_cast<const uint4 *>(sin + (size_t)gy * L + gx0);
+    uint4 vn = make_uint4(0u, 0u, 0u, 0u);
+    if (ly == TW - 1) {
+        const uint32_t gyn = (gy + 1u == L) ? 0u : gy + 1u;
+        vn = *reinterpret_cast<const uint4 *>(sin + (size_t)gyn * L + gx0);
+    }
+    uint32_t ve = 0;
+    if (seg == RPT - 1) {
+        const uint32_t gxe = (gx0 + 16u == L) ? 0u : gx0 + 16u;
+        ve = (uint8_t)sin[(size_t)gy * L + gxe];
+    }
+    load_table<TW>(d, tile, pp, s_tab, tid);
+
+    // flip bits of every tile row: one Philox call per row of TW sites
+    if (tid < (uint32_t)TW) {
+        const uint32_t r0 = (ty * TW + tid) * L + tx * TW;
+        uint32_t w0 = r0 >> 7, w1 = t, w2 = 1u, w3 = 0u;
+        philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
+        const uint32_t off = r0 & 127u;
+        if constexpr (TW == 64) {
+            s_fb[tid] = off == 0u ? (((uint64_t)w1 << 32) | w0) : (((uint64_t)w3 << 32) | w2);
+        } else {
+            const uint32_t q = off >> 5;
+            s_fb[tid] = q == 0 ? w0 : q == 1 ? w1 : q == 2 ? w2 : w3;
+        }
+    }
+    for (uint32_t i = tid; i < (uint32_t)(NS / 2); i += NT) s_sz[i] = 0u;
+    for (uint32_t i = tid; i < (uint32_t)NW; i += NT) s_bf[i] = 0u;
+    if (tid < (uint32_t)((TW + 31) / 32)) {
+        s_eup[tid] = 0u;
+        s_xe[tid] = 0u;
+    }
+    if (tid < 12u) s_hist[tid] = 0u;
+    if (tid == 0) s_xn = 0;
+    __syncthreads();
+
+    // ---- decode the incoming configuration to up-spin masks
+    const uint32_t up = decode16<TW>(v, s_tab);
+    reinterpret_cast<uint16_t *>(s_up)[ly * RPT + seg] = (uint16_t)up;
+    if (ly == TW - 1) {
+        const uint32_t upn = decode16_remote(vn, north, par_prev, d.rspin, nnodes);
+        reinterpret_cast<uint16_t *>(s_up)[TW * RPT + seg] = (uint16_t)upn;
+    }
+    if (seg == RPT - 1) {
+        if (resolve_byte(ve, east, par_prev, d.rspin, nnodes) > 0) atomicOr(&s_eup[ly >> 5], 1u << (ly & 31u));
+    }
+    __syncthreads();
+
+    // ---- bonds (Sec. 2.1) and energy / magnetisation of the incoming spins
+    const Row rowv = s_up[ly];
+    const uint32_t upN = (uint32_t)(s_up[ly + 1] >> x0) & 0xFFFFu;
+    const uint32_t ebit = (s_eup[ly >> 5] >> (ly & 31u)) & 1u;
+    const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
+    const uint32_t upE = (up >> 1) | (nxt << 15);
+    const uint32_t eqE = ~(up ^ upE) & 0xFFFFu;
+    const uint32_t eqN = ~(up ^ upN) & 0xFFFFu;
+    int32_t e_part = 2 * (__popc(eqE) + __popc(eqN)) - 32;
+    int32_t m_part = 2 * __popc(up) - 16;
+    uint32_t rE = 0u, rN = 0u;
+    {
+        const uint32_t c0 = (gy * L + gx0) >> 1;
+        const uint32_t T = d.T;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            uint32_t w0 = c0 + (uint32_t)j, w1 = t, w2 = 0u, w3 = 0u;
+            philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
+            rE |= ((uint32_t)(w0 < T) << (2 * j)) | ((uint32_t)(w2 < T) << (2 * j + 1));
+            rN |= ((uint32_t)(w1 < T) << (2 * j)) | ((uint32_t)(w3 < T) << (2 * j + 1));
+        }
+    }
+    uint32_t bE = eqE & rE, bN = eqN & rN;
+    if (seg == RPT - 1) {
+        if (bE >> 15) atomicOr(&s_xe[ly >> 5], 1u << (ly & 31u));
+        bE &= 0x7FFFu;
+    }
+    if (ly == TW - 1) {
+        reinterpret_cast<uint16_t *>(&s_xn)[seg] = (uint16_t)bN;
+        bN = 0u;
+    }
+    reinterpret_cast<uint16_t *>(s_eb)[ly * RPT + seg] = (uint16_t)bE;
+    reinterpret_cast<uint16_t *>(s_nb)[ly * RPT + seg] = (uint16_t)bN;
+    __syncthreads();
+
+    // ---- row runs: a site starts a run unless bonded to its west neighbour
+    const Row E0 = s_eb[ly];
+    const Row B0 = (Row)~(Row)(E0 << 1);
+    const uint32_t st = (uint32_t)(B0 >> x0) & 0xFFFFu;
+    {
+        uint32_t m = st;
+        while (m) {
+            const uint32_t i = (uint32_t)__ffs((int)m) - 1u;
+            m &= m - 1u;
+            s_par[rowbase + x0 + i] = rowbase + x0 + i;
+        }
+    }
+    __syncthreads();
+
+    // ---- vertical bonds join runs of adjacent rows (one union per group of
+    // vertical bonds that connect the same pair of runs)
+    if (ly + 1u < (uint32_t)TW) {
+        const Row V = s_nb[ly];
+        const Row E1 = s_eb[ly + 1];
+        const Row B1 = (Row)~(Row)(E1 << 1);
+        const Row R = V & (Row)~(Row)((V << 1) & (E0 << 1) & (E1 << 1));
+        uint32_t r = (uint32_t)(R >> x0) & 0xFFFFu;
+        while (r) {
+            const uint32_t i = (uint32_t)__ffs((int)r) - 1u;
+            r &= r - 1u;
+            const uint32_t x = x0 + i;
+            lds_union(s_par, rowbase + hsb_le(B0, x), rowbase + TW + hsb_le(B1, x));
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t m = st;
+        while (m) {
+            const uint32_t i = (uint32_t)__ffs((int)m) - 1u;
+            m &= m - 1u;
+            const uint32_t s = rowbase + x0 + i;
+            atomicMin(&s_par[s], lds_find(s_par, s));
+        }
+    }
+    __syncthreads();
+
+    // ---- cluster sizes and boundary flags, one piece (run fragment) at a time
+    const uint32_t rs0 = hsb_le(B0, x0);
+    {
+        uint32_t pm = st | 1u;
+        uint32_t prev_root = kEmpty, acc = 0u;
+        const bool edge_row = (ly == 0u) || (ly == (uint32_t)TW - 1u);
+        while (pm) {
+            const uint32_t i = (uint32_t)__ffs((int)pm) - 1u;
+            pm &= pm - 1u;
+            const uint32_t j = pm ? (uint32_t)__ffs((int)pm) - 1u : 16u;
+            const uint32_t rs = (i == 0u) ? rs0 : x0 + i;
+            const uint32_t root = s_par[rowbase + rs];
+            if (root != prev_root) {
+                if (acc) atomicAdd(&s_sz[prev_root >> 1], acc << (16u * (prev_root & 1u)));
+                prev_root = root;
+                acc = 0u;
+            }
+            acc += j - i;
+            const bool flag = edge_row || (i == 0u && seg == 0u) || (j == 16u && seg == RPT - 1u);
+            if (flag) atomicOr(&s_bf[root >> 5], 1u << (root & 31u));
+        }
+        if (acc) atomicAdd(&s_sz[prev_root >> 1], acc << (16u * (prev_root & 1u)));
+    }
+    __syncthreads();
+
+    // ---- number the boundary clusters (nodes) in site order
+    if (tid < 64u) {
+        uint32_t wa = 0u, wb = 0u, c;
+        if constexpr (NW == 128) {
+            wa = s_bf[2 * tid];
+            wb = s_bf[2 * tid + 1];
+            c = __popc(wa) + __popc(wb);
+        } else {
+            wa = tid < (uint32_t)NW ? s_bf[tid] : 0u;
+            c = __popc(wa);
+        }
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t n = __shfl_up(incl, o, 64);
+            if (tid >= (uint32_t)o) incl += n;
+        }
+        const uint32_t excl = incl - c;
+        if constexpr (NW == 128) {
+            s_pf[2 * tid] = excl;
+            s_pf[2 * tid + 1] = excl + __popc(wa);
+        } else {
+            if (tid < (uint32_t)NW) s_pf[tid] = excl;
+        }
+        if (tid == 63u) s_k = incl;
+    }
+    __syncthreads();
+
+    // ---- outputs: one byte per site (final spin or node code)
+    uint32_t out[4] = {0u, 0u, 0u, 0u};
+    uint32_t lab[16];
+    uint32_t rootmask = 0u;
+    {
+        uint32_t cur_root = 0u, cur_byte = 0u, cur_lab = 0u;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (q == 0 || ((st >> q) & 1u)) {
+                const uint32_t rs = (q == 0) ? rs0 : x0 + (uint32_t)q;
+                cur_root = s_par[rowbase + rs];
+                const uint32_t w = s_bf[cur_root >> 5];
+                const uint32_t bit = 1u << (cur_root & 31u);
+                if (w & bit) {
+                    const uint32_t k = s_pf[cur_root >> 5] + __popc(w & (bit - 1u));
+                    cur_byte = 2u + k;
+                    cur_lab = 0x80000000u | (tile * kNodeSlots + k);
+                } else {
+                    const uint32_t f = (uint32_t)(s_fb[cur_root / TW] >> (cur_root % TW)) & 1u;
+                    cur_byte = f ? 0xFFu : 0x01u;
+                    cur_lab = (ty * TW + cur_root / TW) * L + tx * TW + cur_root % TW;
+                }
+                if (cur_root == rowbase + x0 + (uint32_t)q) rootmask |= 1u << q;
+            }
+            out[q >> 2] |= cur_byte << (8 * (q & 3));
+            lab[q] = cur_lab;
+        }
+    }
+    *reinterpret_cast<uint4 *>(sout + (size_t)gy * L + gx0) = make_uint4(out[0], out[1], out[2], out[3]);
+    if (d.labels) {
+        uint4 *lp = reinterpret_cast<uint4 *>(d.labels + (size_t)gy * L + gx0);
+        lp[0] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
+        lp[1] = make_uint4(lab[4], lab[5], lab[6], lab[7]);
+        lp[2] = make_uint4(lab[8], lab[9], lab[10], lab[11]);
+        lp[3] = make_uint4(lab[12], lab[13], lab[14], lab[15]);
+    }
+    {
+        // node index of every edge site (all of them belong to nodes)
+        uint8_t *eg = d.edge + (size_t)tile * 4u * TW;
+        if (seg == 0u) eg[0 * TW + ly] = (uint8_t)((out[0] & 0xFFu) - 2u);
+        if (seg == RPT - 1u) eg[1 * TW + ly] = (uint8_t)((out[3] >> 24) - 2u);
+        if (ly == 0u)
+            *reinterpret_cast<uint4 *>(eg + 2 * TW + x0) =
+                make_uint4(out[0] - 0x02020202u, out[1] - 0x02020202u, out[2] - 0x02020202u, out[3] - 0x02020202u);
+        if (ly == (uint32_t)TW - 1u)
+            *reinterpret_cast<uint4 *>(eg + 3 * TW + x0) =
+                make_uint4(out[0] - 0x02020202u, out[1] - 0x02020202u, out[2] - 0x02020202u, out[3] - 0x02020202u);
+    }
+
+    // ---- cluster roots in this segment: nodes out, interior statistics in
+    uint32_t n_int = 0u, max_int = 0u, sq_int = 0u;
+    while (rootmask) {
+        const uint32_t q = (uint32_t)__ffs((int)rootmask) - 1u;
+        rootmask &= rootmask - 1u;
+        const uint32_t root = rowbase + x0 + q;
+        const uint32_t S = (s_sz[root >> 1] >> (16u * (root & 1u))) & 0xFFFFu;
+        const uint32_t w = s_bf[root >> 5];
+        const uint32_t bit = 1u << (root & 31u);
+        if (w & bit) {
+            const uint32_t k = s_pf[root >> 5] + __popc(w & (bit - 1u));
+            const uint32_t node = tile * kNodeSlots + k;
+            d.key[node] = gy * L + gx0 + q;
+            d.nsize[node] = S;
+            par_cur[node] = node;
+        } else {
+            ++n_int;
+            max_int = max(max_int, S);
+            sq_int += S * S;
+            atomicAdd(&s_hist[31 - __clz((int)max(S, 1u))], 1u);
+            if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
+        }
+    }
+
+    // ---- workgroup reductions -> tile partial
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        e_part += __shfl_xor(e_part, o, 64);
+        m_part += __shfl_xor(m_part, o, 64);
+        n_int += __shfl_xor(n_int, o, 64);
+        max_int = max(max_int, (uint32_t)__shfl_xor((int)max_int, o, 64));
+        sq_int += __shfl_xor(sq_int, o, 64);
+    }
+    if ((tid & 63u) == 0u) {
+        s_red[tid >> 6][0] = e_part;
+        s_red[tid >> 6][1] = m_part;
+        s_red[tid >> 6][2] = (int32_t)n_int;
+        s_red[tid >> 6][3] = (int32_t)max_int;
+        s_red[tid >> 6][4] = (int32_t)sq_int;
+    }
+    __syncthreads();
+    if (tid == 0u) {
+        int32_t e = 0, m = 0, n = 0, mx = 0, sq = 0;
+        for (int w = 0; w < NWAVE; ++w) {
+            e += s_red[w][0];
+            m += s_red[w][1];
+            n += s_red[w][2];
+            mx = max(mx, s_red[w][3]);
+            sq += s_red[w][4];
+        }
+        int32_t *tp = d.tpart + (size_t)tile * kTilePart;
+        tp[TP_E] = e;
+        tp[TP_M] = m;
+        tp[TP_N] = n;
+        tp[TP_MAX] = mx;
+        tp[TP_SQ] = sq;
+        for (int b = 0; b < 12; ++b) tp[TP_HIST + b] = (int32_t)s_hist[b];
+        d.nk[pc][tile] = s_k;
+        uint64_t xe = s_xe[0];
+        if constexpr (TW == 64) xe |= (uint64_t)s_xe[1] << 32;
+        d.xb[2u * tile] = xe;
+        d.xb[2u * tile + 1u] = (uint64_t)s_xn;
+    }
+}
+
+// =====================================================================
+// k_union: bonds that leave a tile through its E or N edge join the nodes
+// on both sides (Sec. 2.3, global part).  One wavefront per tile.
+// =====================================================================
+template <int TW>
+__global__ __launch_bounds__(256) void k_union(Dev d) {
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t tile = blockIdx.x * 4u + wv;
+    if (tile >= d.ntiles) return;
+    const uint32_t pc = (uint32_t)(*d.tdev & 1u);
+    uint32_t *par = d.parent[pc];
+    const uint32_t ntx = d.ntx, tx = tile % ntx, ty = tile / ntx;
+    const uint32_t east = ty * ntx + (tx + 1u == ntx ? 0u : tx + 1u);
+    const uint32_t north = (ty + 1u == ntx ? 0u : ty + 1u) * ntx + tx;
+    const uint8_t *eg = d.edge + (size_t)tile * 4u * TW;
+    const uint8_t *ege = d.edge + (size_t)east * 4u * TW;
+    const uint8_t *egn = d.edge + (size_t)north * 4u * TW;
+    const uint64_t xe = d.xb[2u * tile], xn = d.xb[2u * tile + 1u];
+
+    auto one_pass = [&](uint64_t bits, uint32_t i, uint32_t a, uint32_t b) {
+        const bool has = (bits >> i) & 1u;
+        const uint32_t pa = __shfl_up(a, 1, 64);
+        const uint32_t pb = __shfl_up(b, 1, 64);
+        const int ph = __shfl_up((int)has, 1, 64);
+        const bool dup = i > 0u && ph && pa == a && pb == b;
+        if (has && !dup) g_union(par, d.key, a, b);
+    };
+    if constexpr (TW == 64) {
+        one_pass(xe, lane, tile * kNodeSlots + eg[1 * TW + lane], east * kNodeSlots + ege[0 * TW + lane]);
+        one_pass(xn, lane, tile * kNodeSlots + eg[3 * TW + lane], north * kNodeSlots + egn[2 * TW + lane]);
+    } else {
+        const uint32_t i = lane & 31u;
+        const bool isn = lane >= 32u;
+        const uint32_t a = tile * kNodeSlots + (isn ? eg[3 * TW + i] : eg[1 * TW + i]);
+        const uint32_t b = isn ? north * kNodeSlots + egn[2 * TW + i] : east * kNodeSlots + ege[0 * TW + i];
+        one_pass(isn ? xn : xe, i, a, b);
+    }
+}
+
+// =====================================================================
+// k_flatten: every node points at its root; node sizes are summed into the
+// roots, first per workgroup in an LDS hash, then with one global atomic
+// per (workgroup, root).  The structure is final here, so finds only read
+// and the only stores are roots.
+// =====================================================================
+constexpr int kHashSlots = 4096;
+
+__device__ __forceinline__ void hash_add(uint32_t *hk, uint32_t *hv, uint32_t key, uint32_t val,
+                                         uint32_t *global_fallback) {
+    uint32_t h = (key * 2654435761u) >> 20;  // 12 bits
+    for (int probe = 0; probe < 64; ++probe) {
+        const uint32_t cur = lds_load(&hk[h]);
+        if (cur == key) {
+            atomicAdd(&hv[h], val);
+            return;
+        }
+        if (cur == kEmpty) {
+            const uint32_t old = atomicCAS(&hk[h], kEmpty, key);
+            if (old == kEmpty || old == key) {
+                atomicAdd(&hv[h], val);
+                return;
+            }
+        }
+        h = (h + 1u) & (kHashSlots - 1);
+    }
+    atomicAdd(&global_fallback[key], val);
+}
+
+__global__ __launch_bounds__(256) void k_flatten(Dev d) {
+    __shared__ uint32_t hk[kHashSlots];
+    __shared__ uint32_t hv[kHashSlots];
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kHashSlots; i += 256u) {
+        hk[i] = kEmpty;
+        hv[i] = 0u;
+    }
+    __syncthreads();
+    const uint32_t pc = (uint32_t)(*d.tdev & 1u);
+    uint32_t *par = d.parent[pc];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t g0 = blockIdx.x * (uint32_t)kGroupTiles;
+    for (uint32_t tt = wv; tt < (uint32_t)kGroupTiles; tt += 4u) {
+        const uint32_t tile = g0 + tt;
+        if (tile >= d.ntiles) break;
+        const uint32_t K = min(d.nk[pc][tile], 252u);
+        for (uint32_t k = lane; k < K; k += 64u) {
+            const uint32_t node = tile * kNodeSlots + k;
+            const uint32_t r = g_root(par, node);
+            if (r != node) {
+                g_store(&par[node], r);
+                hash_add(hk, hv, r, d.nsize[node], d.nsize);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kHashSlots; i += 256u) {
+        const uint32_t k = hk[i];
+        if (k != kEmpty) atomicAdd(&d.nsize[k], hv[i]);
+    }
+}
+
+// Canonical labels of sites of cross-tile clusters (only with SW_FLAG_LABELS).
+__global__ __launch_bounds__(256) void k_relabel(Dev d) {
+    const size_t n = (size_t)d.L * d.L;
+    const uint32_t pc = (uint32_t)(*d.tdev & 1u);
+    const uint32_t *par = d.parent[pc];
+    const uint32_t nnodes = d.ntiles * kNodeSlots;
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const uint32_t l = d.labels[i];
+        if (l & 0x80000000u) {
+            uint32_t node = l & 0x7FFFFFFFu;
+            node = node < nnodes ? node : 0u;
+            uint32_t r = par[node];
+            r = r < nnodes ? r : 0u;
+            d.labels[i] = d.key[r];
+        }
+    }
+}
+
+// =====================================================================
+// k_roots: new spin of every cross-tile cluster (Sec. 2.4) and the cluster
+// statistics of the workgroup's tiles -> group partial.
+// =====================================================================
+__global__ __launch_bounds__(256) void k_roots(Dev d) {
+    __shared__ uint32_t s_hist[33];
+    __shared__ uint64_t s_red[4][5];
+    if (threadIdx.x < 33u) s_hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint64_t tsw = *d.tdev;
+    const uint32_t t = (uint32_t)tsw, pc = (uint32_t)(tsw & 1u);
+    const uint32_t *par = d.parent[pc];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t g0 = blockIdx.x * (uint32_t)kGroupTiles;
+    uint64_t n = 0, mx = 0, sq = 0;
+    int64_t e = 0, m = 0;
+    for (uint32_t tt = wv; tt < (uint32_t)kGroupTiles; tt += 4u) {
+        const uint32_t tile = g0 + tt;
+        if (tile >= d.ntiles) break;
+        const uint32_t K = min(d.nk[pc][tile], 252u);
+        for (uint32_t k = lane; k < K; k += 64u) {
+            const uint32_t node = tile * kNodeSlots + k;
+            if (par[node] == node) {
+                const uint32_t S = d.nsize[node];
+                d.rspin[node] = cluster_spin(d.key[node], t, d.seed_lo, d.seed_hi);
+                ++n;
+                mx = max(mx, (uint64_t)S);
+                sq += (uint64_t)S * S;
+                atomicAdd(&s_hist[31 - __clz((int)max(S, 1u))], 1u);
+                if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
+            }
+        }
+    }
+    if (threadIdx.x < (uint32_t)kGroupTiles) {
+        const uint32_t tile = g0 + threadIdx.x;
+        if (tile < d.ntiles) {
+            const int32_t *tp = d.tpart + (size_t)tile * kTilePart;
+            e += tp[TP_E];
+            m += tp[TP_M];
+            n += (uint32_t)tp[TP_N];
+            mx = max(mx, (uint64_t)(uint32_t)tp[TP_MAX]);
+            sq += (uint32_t)tp[TP_SQ];
+            for (int b = 0; b < 12; ++b)
+                if (tp[TP_HIST + b]) atomicAdd(&s_hist[b], (uint32_t)tp[TP_HIST + b]);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        n += __shfl_xor(n, o, 64);
+        mx = max(mx, (uint64_t)__shfl_xor((unsigned long long)mx, o, 64));
+        sq += __shfl_xor(sq, o, 64);
+        e += __shfl_xor(e, o, 64);
+        m += __shfl_xor(m, o, 64);
+    }
+    if (lane == 0u) {
+        s_red[wv][0] = n;
+        s_red[wv][1] = mx;
+        s_red[wv][2] = sq;
+        s_red[wv][3] = (uint64_t)e;
+        s_red[wv][4] = (uint64_t)m;
+    }
+    __syncthreads();
+    uint64_t *gp = d.gpart + (size_t)blockIdx.x * kGroupPart;
+    if (threadIdx.x == 0u) {
+        uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+        for (int w = 0; w < 4; ++w) {
+            a0 += s_red[w][0];
+            a1 = max(a1, s_red[w][1]);
+            a2 += s_red[w][2];
+            a3 += s_red[w][3];
+            a4 += s_red[w][4];
+        }
+        gp[GP_N] = a0;
+        gp[GP_MAX] = a1;
+        gp[GP_SQ] = a2;
+        gp[GP_E] = a3;
+        gp[GP_M] = a4;
+    }
+    if (threadIdx.x < 33u) gp[GP_HIST + threadIdx.x] = s_hist[threadIdx.x];
+}
+
+// =====================================================================
+// k_record: fold group partials (mode 0, end of a sweep) or tile partials
+// (mode 1, end of k_resolve) into the record ring; the last workgroup to
+// finish writes the record and clears the accumulator.
+// =====================================================================
+__global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode) {
+    __shared__ uint64_t s_acc[GP_END];
+    __shared__ int s_last;
+    const uint32_t tid = threadIdx.x;
+    if (tid < (uint32_t)GP_END) s_acc[tid] = 0u;
+    __syncthreads();
+    const uint32_t item = blockIdx.x * 256u + tid;
+    if (item < nitems) {
+        if (mode == 0) {
+            const uint64_t *gp = d.gpart + (size_t)item * kGroupPart;
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_N]), (unsigned long long)gp[GP_N]);
+            atomicMax(reinterpret_cast<unsigned long long *>(&s_acc[GP_MAX]), (unsigned long long)gp[GP_MAX]);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_SQ]), (unsigned long long)gp[GP_SQ]);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_E]), (unsigned long long)gp[GP_E]);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_M]), (unsigned long long)gp[GP_M]);
+            for (int b = 0; b < 33; ++b)
+                if (gp[GP_HIST + b])
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_HIST + b]),
+                              (unsigned long long)gp[GP_HIST + b]);
+        } else {
+            const int32_t *tp = d.tpart + (size_t)item * kTilePart;
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_E]), (unsigned long long)(int64_t)tp[TP_E]);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_M]), (unsigned long long)(int64_t)tp[TP_M]);
+        }
+    }
+    __syncthreads();
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(d.acc);
+    if (tid < (uint32_t)GP_END && s_acc[tid] != 0u) {
+        if (tid == (uint32_t)GP_MAX)
+            atomicMax(&acc[tid], (unsigned long long)s_acc[tid]);
+        else
+            atomicAdd(&acc[tid], (unsigned long long)s_acc[tid]);
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0u) {
+        const unsigned long long old = atomicAdd(&acc[ACC_COUNT], 1ull);
+        s_last = (old == (unsigned long long)gridDim.x - 1ull) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (tid == 0u) {
+        uint64_t v[GP_END];
+        for (int i = 0; i < GP_END; ++i) {
+            v[i] = __hip_atomic_load(&acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&acc[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __hip_atomic_store(&acc[ACC_COUNT], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t tsw = *d.tdev;
+        if (mode == 0) {
+            sw_obs *rec = &d.ring[tsw % d.ring_cap];
+            rec->sweep = tsw;
+            rec->n_clusters = v[GP_N];
+            rec->max_cluster = v[GP_MAX];
+            rec->sum_sq_sizes = v[GP_SQ];
+            for (int b = 0; b < 33; ++b) rec->hist_log2[b] = v[GP_HIST + b];
+        }
+        if (tsw >= 1u) {
+            // observables of the configuration that sweep tsw-1 left
+            sw_obs *prev = &d.ring[(tsw - 1u) % d.ring_cap];
+            const int64_t e = (int64_t)v[GP_E];
+            prev->e_sum = e;
+            prev->energy = -d.J * (double)e;
+            prev->m_sum = (int64_t)v[GP_M];
+        }
+        if (mode == 0) *d.tdev = tsw + 1u;
+        __threadfence();
+    }
+}
+
+// =====================================================================
+// k_resolve: replace node codes by final spins in place and measure the
+// configuration (runs once at the end of every sw_sweep call).
+// =====================================================================
+template <int TW>
+__global__ __launch_bounds__(TW *TW / 16) void k_resolve(Dev d) {
+    constexpr int NT = TW * TW / 16;
+    constexpr uint32_t RPT = TW / 16;
+    constexpr int NWAVE = (NT + 63) / 64;
+    using Row = typename RowOf<TW>::T;
+    __shared__ int8_t s_tab[256];
+    __shared__ Row s_up[TW + 1];
+    __shared__ uint32_t s_eup[(TW + 31) / 32];
+    __shared__ int32_t s_red[NWAVE][2];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t L = d.L, ntx = d.ntx;
+    const uint32_t tile = tile_of_block(blockIdx.x, d.ntiles);
+    const uint32_t tx = tile % ntx, ty = tile / ntx;
+    const uint64_t tsw = *d.tdev;
+    const uint32_t pc = (uint32_t)(tsw & 1u), pp = pc ^ 1u;
+    int8_t *sp = d.spins[pc];
+    const uint32_t *par_prev = d.parent[pp];
+    const uint32_t nnodes = d.ntiles * kNodeSlots;
+    const uint32_t ly = tid / RPT, seg = tid % RPT, x0 = seg * 16u;
+    const uint32_t gy = ty * TW + ly, gx0 = tx * TW + x0;
+    const uint32_t east = ty * ntx + (tx + 1u == ntx ? 0u : tx + 1u);
+    const uint32_t north = (ty + 1u == ntx ? 0u : ty + 1u) * ntx + tx;
+
+    const uint4 v = *reinterpret_cast<const uint4 *>(sp + (size_t)gy * L + gx0);
+    uint4 vn = make_uint4(0u, 0u, 0u, 0u);
+    if (ly == TW - 1) {
+        const uint32_t gyn = (gy + 1u == L) ? 0u : gy + 1u;
+        vn = *reinterpret_cast<const uint4 *>(sp + (size_t)gyn * L + gx0);
+    }
+    uint32_t ve = 0;
+    if (seg == RPT - 1) {
+        const uint32_t gxe = (gx0 + 16u == L) ? 0u : gx0 + 16u;
+        ve = (uint8_t)sp[(size_t)gy * L + gxe];
+    }
+    load_table<TW>(d, tile, pp, s_tab, tid);
+    if (tid < (uint32_t)((TW + 31) / 32)) s_eup[tid] = 0u;
+    __syncthreads();
+    const uint32_t up = decode16<TW>(v, s_tab);
+    reinterpret_cast<uint16_t *>(s_up)[ly * RPT + seg] = (uint16_t)up;
+    if (ly == TW - 1) {
+        const uint32_t upn = decode16_remote(vn, north, par_prev, d.rspin, nnodes);
+        reinterpret_cast<uint16_t *>(s_up)[TW * RPT + seg] = (uint16_t)upn;
+    }
+    if (seg == RPT - 1) {
+        if (resolve_byte(ve, east, par_prev, d.rspin, nnodes) > 0) atomicOr(&s_eup[ly >> 5], 1u << (ly & 31u));
+    }
+    __syncthreads();
+    const Row rowv = s_up[ly];
+    const uint32_t upN = (uint32_t)(s_up[ly + 1] >> x0) & 0xFFFFu;
+    const uint32_t ebit = (s_eup[ly >> 5] >> (ly & 31u)) & 1u;
+    const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
+    const uint32_t upE = (up >> 1) | (nxt << 15);
+    int32_t e_part = 2 * (__popc(~(up ^ upE) & 0xFFFFu) + __popc(~(up ^ upN) & 0xFFFFu)) - 32;
+    int32_t m_part = 2 * __popc(up) - 16;
+    uint32_t out[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) out[q >> 2] |= (((up >> q) & 1u) ? 0x01u : 0xFFu) << (8 * (q & 3));
+    *reinterpret_cast<uint4 *>(sp + (size_t)gy * L + gx0) = make_uint4(out[0], out[1], out[2], out[3]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        e_part += __shfl_xor(e_part, o, 64);
+        m_part += __shfl_xor(m_part, o, 64);
+    }
+    if ((tid & 63u) == 0u) {
+        s_red[tid >> 6][0] = e_part;
+        s_red[tid >> 6][1] = m_part;
+    }
+    __syncthreads();
+    if (tid == 0u) {
+        int32_t e = 0, m = 0;
+        for (int w = 0; w < NWAVE; ++w) {
+            e += s_red[w][0];
+            m += s_red[w][1];
+        }
+        d.tpart[(size_t)tile * kTilePart + TP_E] = e;
+        d.tpart[(size_t)tile * kTilePart + TP_M] = m;
+    }
+}
+
+// Initial spins (Fig. 1): hot = bit 0 of word 0 of Philox({s, 0, 2, 0}),
+// cold = all +1.  16 sites per thread.
+__global__ __launch_bounds__(256) void k_init(Dev d, int cold) {
+    const size_t n16 = (size_t)d.L * d.L / 16u;
+    const uint32_t pc = (uint32_t)(*d.tdev & 1u);
+    int8_t *sp = d.spins[pc];
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256) {
+        uint32_t out[4] = {0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u};
+        if (!cold) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                uint32_t w0 = (uint32_t)(i * 16u + q), w1 = 0u, w2 = 2u, w3 = 0u;
+                philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
+                if (w0 & 1u) out[q >> 2] |= 0xFFu << (8 * (q & 3));
+            }
+        }
+        *reinterpret_cast<uint4 *>(sp + i * 16u) = make_uint4(out[0], out[1], out[2], out[3]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_u64(uint64_t *p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
+inline uint32_t grid_for(size_t n, uint32_t per_block, uint32_t cap) {
+    size_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+}  // namespace
+
+hipError_t launch_init(const Dev &d, int cold, hipStream_t s) {
+    const size_t n16 = (size_t)d.L * d.L / 16u;
+    k_init<<<grid_for(n16, 256, 65536), 256, 0, s>>>(d, cold);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const Dev &d, hipStream_t s) {
+    const size_t n = (size_t)d.L * d.L;
+    if (d.dense) k_zero_u64<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(d.dense, n + 1);
+    if (d.tw == 64) {
+        k_tile<64><<<d.ntiles, 256, 0, s>>>(d);
+        k_union<64><<<(d.ntiles + 3) / 4, 256, 0, s>>>(d);
+    } else {
+        k_tile<32><<<d.ntiles, 64, 0, s>>>(d);
+        k_union<32><<<(d.ntiles + 3) / 4, 256, 0, s>>>(d);
+    }
+    k_flatten<<<d.ngroups, 256, 0, s>>>(d);
+    if (d.labels) k_relabel<<<grid_for(n, 256, 65536), 256, 0, s>>>(d);
+    k_roots<<<d.ngroups, 256, 0, s>>>(d);
+    k_record<<<(d.ngroups + 255) / 256, 256, 0, s>>>(d, d.ngroups, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve(const Dev &d, hipStream_t s) {
+    if (d.tw == 64)
+        k_resolve<64><<<d.ntiles, 256, 0, s>>>(d);
+    else
+        k_resolve<32><<<d.ntiles, 64, 0, s>>>(d);
+    k_record<<<(d.ntiles + 255) / 256, 256, 0, s>>>(d, d.ntiles, 1);
+    return hipGetLastError();
+}
+
+}  // namespace swmi

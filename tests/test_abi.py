@@ -1,0 +1,73 @@
+"""The C ABI library loads and exports every symbol that include/swmi.h
+declares; host-only entry points behave as documented (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2302_14720_amd as sw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "swmi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sw_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(sw.LIB_PATH):
+        from paper_2302_14720_amd import build
+        build.build()
+    return sw.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "sw_create" in names and "sw_sweep" in names and "sw_observables" in names
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in sw._SIGNATURES, f"binding lacks {name}"
+
+
+def test_binding_covers_only_declared_symbols():
+    assert sorted(sw._SIGNATURES) == _declared()
+
+
+def test_workspace_sizes_and_validation(lib):
+    n64 = sw.sw_workspace_bytes(64)
+    n1024 = sw.sw_workspace_bytes(1024)
+    assert n64 > 2 * 64 * 64 and n1024 > 2 * 1024 * 1024
+    assert n1024 > n64
+    for bad in (0, 16, 33, 100, 65536):
+        assert sw.sw_workspace_bytes(bad) == 0
+    cfg = sw.sw_config_init(96, 0.44, 1.0, 1)
+    assert sw.sw_workspace_bytes_ex(cfg) > 0
+    cfg.tile = 64  # 96 is not a multiple of 64
+    assert sw.sw_workspace_bytes_ex(cfg) == 0
+    assert "tile 64" in sw.sw_last_error()
+    cfg = sw.sw_config_init(64, -1.0, 1.0, 1)
+    assert sw.sw_workspace_bytes_ex(cfg) == 0
+    cfg = sw.sw_config_init(64, 0.4, 0.0, 1)
+    assert sw.sw_workspace_bytes_ex(cfg) == 0
+    cfg = sw.sw_config_init(64, float("nan"), 1.0, 1)
+    assert sw.sw_workspace_bytes_ex(cfg) == 0
+    cfg = sw.sw_config_init(64, 0.4, 1.0, 1, flags=sw.SW_FLAG_LABELS | sw.SW_FLAG_DENSE_HIST)
+    plain = sw.sw_config_init(64, 0.4, 1.0, 1)
+    assert sw.sw_workspace_bytes_ex(cfg) >= sw.sw_workspace_bytes_ex(plain) + 64 * 64 * 4 + (64 * 64 + 1) * 8
+    cfg = sw.sw_config_init(64, 0.4, 1.0, 1, flags=8)
+    assert sw.sw_workspace_bytes_ex(cfg) == 0
+
+
+def test_create_rejects_bad_arguments_before_touching_the_gpu(lib):
+    h = ctypes.c_void_p()
+    assert lib.sw_create(48, 0.4, 1.0, 1, ctypes.byref(h)) == sw.SW_EINVAL
+    assert h.value is None
+    assert lib.sw_create(64, 0.4, -1.0, 1, ctypes.byref(h)) == sw.SW_EINVAL
+    assert lib.sw_create_in(64, 0.4, 1.0, 1, None, 0, None, ctypes.byref(h)) == sw.SW_EINVAL
+    assert lib.sw_sweep(None, 1) == sw.SW_EINVAL
+    assert lib.sw_observables(None, None) == sw.SW_EINVAL
+    lib.sw_destroy(None)  # no-op

@@ -1,0 +1,224 @@
+"""Benchmark: Swendsen-Wang site-updates/s of the 2D Ising model at
+L = 16384, beta_c, on one MI355X.
+
+One step = one full sweep of the lattice (bond formation, cluster labelling,
+new cluster spins, per-sweep record: Sec. 2 of the paper).  The timed region
+is `steps` consecutive sweeps of one device-resident lattice, issued as one
+sw_sweep call (graph-replayed sweeps plus the closing pass that leaves final
++-1 spins and measures them), bracketed by device synchronisation.
+
+Prints one JSON line.  Besides the headline rate it reports the roofline of
+the dominant kernel (per-kernel durations from HIP events on the sim's own
+stream, in a profiled continuation of the same chain), the cold-start rate of
+the first sweeps, and the CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SW site-updates/s at L=16384 βc (1 GPU, % HBM roofline); batched vs plain"
+BETA_C = math.log(1.0 + math.sqrt(2.0)) / 2.0
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+# Integer VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one
+# 32-bit integer op per lane per clock; packed math does not apply to the
+# integer multiplies and xors that dominate here).
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# Algorithmic work of k_tile per site.  Bytes: the spin byte read and the
+# spin byte written.  Integer ops: Philox4x32-10 costs 10 rounds x (2 wide
+# multiplies + 4 xors) = 60 ops per call; a site needs 1/2 call for its two
+# bond words plus 1/TW of a call for the flip bits of its tile row.
+TILE_BYTES_PER_SITE = 2.0
+PHILOX_OPS = 60.0
+
+
+def kernel_source_sha() -> str:
+    p = os.path.join(ROOT, "paper_2302_14720_amd", "csrc", "sw_kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def load_traffic(L: int):
+    """HBM bytes per k_tile launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"k_tile_L{L}_counters.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(L: int, seed: int):
+    import oracle
+
+    T = oracle.threshold(BETA_C, 1.0)
+    spins = oracle.init(L, seed)
+    t0 = time.perf_counter()
+    oracle.run(L, 1.0, T, seed, 0, 1, spins)
+    dt = time.perf_counter() - t0
+    return {
+        "value": L * L / dt,
+        "unit": "site-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one sweep of the L={L} beta_c lattice from a hot start (seed {seed}); "
+                  f"sequential C oracle, {dt:.1f} s",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--L", type=int, default=16384)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--profile-sweeps", type=int, default=20)
+    ap.add_argument("--cold-sweeps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the per-kernel profile and the cold-start leg (for counter runs)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (reference for "
+                         "HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(the sweep of one lattice is a single-GPU workload here)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2302_14720_amd as sw
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        return 1
+    L, N = args.L, args.L * args.L
+    print(f"[bench] L={L} beta_c hot start seed={args.seed}: warmup {args.warmup}, "
+          f"timed {args.steps} sweeps", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy_mib > 0:
+        nb = args.calibrate_copy_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] calibration copy of {nb} bytes done", file=sys.stderr, flush=True)
+
+    sim = sw.Sim(L, BETA_C, 1.0, args.seed, init=sw.SW_INIT_HOT)
+    sim.sweep(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.sweep(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = N * args.steps / dt
+    rec = sim.observables()
+    # integer invariants of the last record
+    assert (int(rec["e_sum"]) - 2 * N) % 4 == 0 and (int(rec["m_sum"]) - N) % 2 == 0
+    assert int(rec["hist_log2"].sum()) == int(rec["n_clusters"])
+    print(f"[bench] timed: {dt * 1e3:.2f} ms, {value:.4e} site-updates/s", file=sys.stderr, flush=True)
+
+    tw = sim.tile
+    if args.no_extras:
+        sim.close()
+        print(json.dumps({"metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+                          "note": "counter run: no per-kernel profile, cold start or CPU baseline"}))
+        return 0
+    prof = sim.profile(args.profile_sweeps)
+    sim.close()
+    print(f"[bench] kernel ms: {prof}", file=sys.stderr, flush=True)
+
+    # cold start: the first sweeps carry one near-spanning cluster
+    cold = sw.Sim(L, BETA_C, 1.0, 3, init=sw.SW_INIT_COLD)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    cold.sweep(args.cold_sweeps)
+    cold.sync()
+    cdt = time.perf_counter() - c0
+    crec = cold.series(0, 1)[0]
+    cold.close()
+
+    per_sweep = {k: v for k, v in prof.items() if k != "resolve"}
+    dom = max(per_sweep, key=per_sweep.get)
+    t_dom = per_sweep[dom] * 1e-3
+    philox_per_site = 0.5 + 1.0 / tw
+    alu_ops = philox_per_site * PHILOX_OPS * N
+    tile_bytes = TILE_BYTES_PER_SITE * N
+    if dom == "tile":
+        hbm_ach = tile_bytes / t_dom / 1e9
+        alu_ach = alu_ops / t_dom / 1e12
+        hbm_frac = hbm_ach / HBM_PEAK_GBS
+        alu_frac = alu_ach / ALU_PEAK_TOPS
+        traffic = load_traffic(L)
+        if alu_frac >= hbm_frac:
+            roofline = {"bound": "alu", "achieved": alu_ach, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                        "frac": alu_frac, "traffic": traffic}
+        else:
+            roofline = {"bound": "hbm", "achieved": hbm_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": hbm_frac, "traffic": traffic}
+        roofline.update({"kernel": "k_tile", "kernel_ms": per_sweep[dom],
+                         "hbm_achieved_GBs": hbm_ach, "hbm_frac": hbm_frac,
+                         "alu_achieved_Tops": alu_ach, "alu_frac": alu_frac})
+    else:
+        roofline = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
+                    "traffic": None, "kernel": dom, "kernel_ms": per_sweep[dom]}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"plain SW sweep, 2D Ising, L={L} periodic (N={N}), J=1, beta=beta_c, "
+                        f"hot start seed {args.seed}, int8 spins, Philox4x32-10",
+            "L": L, "beta": BETA_C, "J": 1.0, "tile": tw, "start": "hot",
+        },
+        # site-updates/s x 12 B (the classic bond/label/flip stream model) / 8 TB/s
+        "effective_roofline_12B_frac": value * 12.0 / (HBM_PEAK_GBS * 1e9),
+        "roofline": roofline,
+        "kernel_ms": prof,
+        "cold_start": {"sweeps": args.cold_sweeps, "value": N * args.cold_sweeps / cdt,
+                       "ms_per_step": cdt * 1e3 / args.cold_sweeps,
+                       "first_sweep_max_cluster": int(crec["max_cluster"])},
+        "batched": None,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on one L=%d sweep" % L, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(L, args.seed)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

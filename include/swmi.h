@@ -129,6 +129,17 @@ int sw_reset(sw_sim *sim, int init_mode);
  * (Sec. 2: bonds, clusters, new spins and the record of each sweep). */
 int sw_sweep(sw_sim *sim, int64_t n);
 
+/* Measurement aid: runs n >= 1 sweeps exactly as sw_sweep does (same
+ * kernels, same results, same records), but launches the kernels one by one
+ * with HIP events between them on the sim's stream and waits after each
+ * sweep.  ms[0..4] receive the average duration in milliseconds of the five
+ * kernels of a sweep -- 0: bonds + tile-local clusters (Sec. 2.1, 2.3),
+ * 1: cross-tile unions, 2: flattening and cluster sizes, 3: spins of
+ * cross-tile clusters (Sec. 2.4) and statistics, 4: the record (Sec. 2.5) --
+ * and ms[5] the closing pass that writes final spins and measures them.
+ * nk (the length of ms) must be >= 6; extra entries are zeroed. */
+int sw_profile(sw_sim *sim, int64_t n, double *ms, int32_t nk);
+
 /* Waits for all enqueued work of the sim. */
 int sw_sync(sw_sim *sim);
 

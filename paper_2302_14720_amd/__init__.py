@@ -70,6 +70,7 @@ _SIGNATURES = {
     "sw_reset": (ctypes.c_int, [_P, ctypes.c_int]),
     "sw_sweep": (ctypes.c_int, [_P, ctypes.c_int64]),
     "sw_sync": (ctypes.c_int, [_P]),
+    "sw_profile": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_int32]),
     "sw_observables": (ctypes.c_int, [_P, _P]),
     "sw_series": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P]),
     "sw_cluster_hist": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
@@ -161,6 +162,15 @@ def sw_sync(h: int) -> None:
     _check(lib().sw_sync(h))
 
 
+PROFILE_STAGES = ("tile", "union", "flatten", "roots", "record", "resolve")
+
+
+def sw_profile(h: int, n: int) -> dict:
+    ms = np.zeros(len(PROFILE_STAGES), dtype=np.float64)
+    _check(lib().sw_profile(h, n, _ptr(ms), ms.size))
+    return dict(zip(PROFILE_STAGES, ms.tolist()))
+
+
 def sw_observables(h: int) -> np.void:
     out = np.zeros(1, dtype=OBS_DTYPE)
     _check(lib().sw_observables(h, _ptr(out)))
@@ -248,6 +258,9 @@ class Sim:
 
     def observables(self):
         return sw_observables(self.handle)
+
+    def profile(self, n: int) -> dict:
+        return sw_profile(self.handle, n)
 
     def series(self, first: int, count: int) -> np.ndarray:
         return sw_series(self.handle, first, count)

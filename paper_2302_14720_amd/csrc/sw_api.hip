@@ -357,6 +357,54 @@ int sw_sweep(sw_sim *s, int64_t n) {
     return SW_OK;
 }
 
+int sw_profile(sw_sim *s, int64_t n, double *ms, int32_t nk) {
+    if (!s || !ms) return fail(SW_EINVAL, "sim or ms is NULL");
+    if (n < 1) return fail(SW_EINVAL, "n must be >= 1");
+    if (nk < swmi::kStages + 1) return fail(SW_ERANGE, "nk must be >= 6");
+    int rc = ensure_device(s);
+    if (rc != SW_OK) return rc;
+    constexpr int kEv = swmi::kStages + 1;
+    hipEvent_t ev[kEv];
+    for (int i = 0; i < kEv; ++i) {
+        const hipError_t e = hipEventCreate(&ev[i]);
+        if (e != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    double acc[swmi::kStages + 1] = {0};
+    hipError_t e = hipSuccess;
+    for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
+        e = hipEventRecord(ev[0], s->stream);
+        for (int st = 0; st < swmi::kStages && e == hipSuccess; ++st) {
+            e = swmi::launch_stage(s->dev, st, s->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[st + 1], s->stream);
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[kEv - 1]);
+        for (int st = 0; st < swmi::kStages && e == hipSuccess; ++st) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, ev[st], ev[st + 1]);
+            acc[st] += t;
+        }
+    }
+    if (e == hipSuccess) {
+        e = hipEventRecord(ev[0], s->stream);
+        if (e == hipSuccess) e = swmi::launch_resolve(s->dev, s->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+        acc[swmi::kStages] = t;
+    }
+    for (int i = 0; i < kEv; ++i) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return hip_fail(e, "sw_profile");
+    s->next_sweep += (uint64_t)n;
+    for (int st = 0; st < swmi::kStages; ++st) ms[st] = acc[st] / (double)n;
+    ms[swmi::kStages] = acc[swmi::kStages];
+    for (int32_t i = swmi::kStages + 1; i < nk; ++i) ms[i] = 0.0;
+    return SW_OK;
+}
+
 int sw_sync(sw_sim *s) {
     if (!s) return fail(SW_EINVAL, "sim is NULL");
     int rc = ensure_device(s);

@@ -60,7 +60,10 @@ struct Dev {
     double J;
 };
 
+constexpr int kStages = 5;  // kernels of one sweep, in stream order
+
 hipError_t launch_init(const Dev &d, int cold, hipStream_t s);
+hipError_t launch_stage(const Dev &d, int stage, hipStream_t s);
 hipError_t launch_sweep(const Dev &d, hipStream_t s);
 hipError_t launch_resolve(const Dev &d, hipStream_t s);
 

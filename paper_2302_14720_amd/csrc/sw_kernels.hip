@@ -155,15 +155,8 @@ __device__ __forceinline__ uint32_t byte_at(const uint4 &v, int q) {
     return (w >> (8 * (q & 3))) & 0xFFu;
 }
 
-// Shared front end of k_tile and k_resolve: load the tile's spin bytes and
-// its E / N halo, decode them to up-spin bit masks.
-template <int TW>
-struct TileFront {
-    using Row = typename RowOf<TW>::T;
-    static constexpr int NT = TW * TW / 16;
-    static constexpr int RPT = TW / 16;
-};
-
+// Shared front end of k_tile and k_resolve: the table that maps this tile's
+// node codes of the previous sweep to spins.
 template <int TW>
 __device__ __forceinline__ void load_table(const Dev &d, uint32_t tile, uint32_t pp, int8_t *s_tab,
                                            uint32_t tid) {
@@ -941,21 +934,44 @@ hipError_t launch_init(const Dev &d, int cold, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const Dev &d, hipStream_t s) {
+hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
     const size_t n = (size_t)d.L * d.L;
-    if (d.dense) k_zero_u64<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(d.dense, n + 1);
-    if (d.tw == 64) {
-        k_tile<64><<<d.ntiles, 256, 0, s>>>(d);
-        k_union<64><<<(d.ntiles + 3) / 4, 256, 0, s>>>(d);
-    } else {
-        k_tile<32><<<d.ntiles, 64, 0, s>>>(d);
-        k_union<32><<<(d.ntiles + 3) / 4, 256, 0, s>>>(d);
+    switch (stage) {
+    case 0:  // bonds + tile-local clusters
+        if (d.dense) k_zero_u64<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(d.dense, n + 1);
+        if (d.tw == 64)
+            k_tile<64><<<d.ntiles, 256, 0, s>>>(d);
+        else
+            k_tile<32><<<d.ntiles, 64, 0, s>>>(d);
+        break;
+    case 1:  // cross-tile unions
+        if (d.tw == 64)
+            k_union<64><<<(d.ntiles + 3) / 4, 256, 0, s>>>(d);
+        else
+            k_union<32><<<(d.ntiles + 3) / 4, 256, 0, s>>>(d);
+        break;
+    case 2:  // flatten + cluster sizes
+        k_flatten<<<d.ngroups, 256, 0, s>>>(d);
+        if (d.labels) k_relabel<<<grid_for(n, 256, 65536), 256, 0, s>>>(d);
+        break;
+    case 3:  // spins of cross-tile clusters, statistics
+        k_roots<<<d.ngroups, 256, 0, s>>>(d);
+        break;
+    case 4:  // record
+        k_record<<<(d.ngroups + 255) / 256, 256, 0, s>>>(d, d.ngroups, 0);
+        break;
+    default:
+        return hipErrorInvalidValue;
     }
-    k_flatten<<<d.ngroups, 256, 0, s>>>(d);
-    if (d.labels) k_relabel<<<grid_for(n, 256, 65536), 256, 0, s>>>(d);
-    k_roots<<<d.ngroups, 256, 0, s>>>(d);
-    k_record<<<(d.ngroups + 255) / 256, 256, 0, s>>>(d, d.ngroups, 0);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep(const Dev &d, hipStream_t s) {
+    for (int stage = 0; stage < kStages; ++stage) {
+        const hipError_t e = launch_stage(d, stage, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_resolve(const Dev &d, hipStream_t s) {

@@ -18,8 +18,9 @@ __device__ __forceinline__ void philox10(uint32_t &x0, uint32_t &x1, uint32_t &x
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)0xD2511F53u * x0;
         const uint64_t pb = (uint64_t)0xCD9E8D57u * x2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ x1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ x3 ^ k1;
+        // three-input xor in one v_bitop3 (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), x1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), x3, k1, 0x96);
         x1 = (uint32_t)pb;
         x3 = (uint32_t)pa;
         x0 = n0;
@@ -53,6 +54,19 @@ __device__ __forceinline__ uint32_t hsb_le(uint32_t B, uint32_t x) {
     return 31u - (uint32_t)__clz((int)m);
 }
 
+// Length of the run that starts at x (B: run-start mask of the row, bit x set).
+template <typename Row>
+__device__ __forceinline__ uint32_t run_len_row(Row B, uint32_t x) {
+    constexpr uint32_t W = sizeof(Row) * 8;
+    const Row above = x + 1u < W ? (Row)(B & (Row)(~(Row)0 << (x + 1u))) : (Row)0;
+    uint32_t next;
+    if constexpr (sizeof(Row) == 8)
+        next = above ? (uint32_t)__ffsll((long long)above) - 1u : W;
+    else
+        next = above ? (uint32_t)__ffs((int)above) - 1u : W;
+    return next - x;
+}
+
 // Workgroup b runs on XCD b % 8; give each XCD a contiguous band of tiles so
 // that neighbouring tiles (which share halo rows and cache lines) meet in
 // the same L2.
@@ -78,6 +92,46 @@ __device__ __forceinline__ uint32_t lds_find(uint32_t *par, uint32_t a) {
         if (gp == p) return p;
         atomicMin(&par[a], gp);
         a = gp;
+    }
+}
+// Union of the sets of a and b.  Both finds advance together (their LDS
+// loads overlap) and halve their paths with min-updates; the larger root is
+// then linked under the smaller one by compare-and-swap, retrying if another
+// lane linked it first.
+__device__ __forceinline__ void lds_union2(uint32_t *par, uint32_t a, uint32_t b) {
+    while (true) {
+        while (true) {
+            const uint32_t pa = lds_load(&par[a]), pb = lds_load(&par[b]);
+            const bool ra = pa == a, rb = pb == b;
+            if (ra && rb) break;
+            if (!ra) {
+                const uint32_t ga = lds_load(&par[pa]);
+                if (ga != pa) atomicMin(&par[a], ga);
+                a = ga;
+            }
+            if (!rb) {
+                const uint32_t gb = lds_load(&par[pb]);
+                if (gb != pb) atomicMin(&par[b], gb);
+                b = gb;
+            }
+        }
+        if (a == b) return;
+        const uint32_t hi = max(a, b), lo = min(a, b);
+        uint32_t expected = hi;
+        if (__hip_atomic_compare_exchange_strong(&par[hi], &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+        a = lo;
+        b = expected;
+    }
+}
+// Root of a once the unions are done (read-only; the high half of a root's
+// word may already hold its cluster size).
+__device__ __forceinline__ uint32_t lds_root(const uint32_t *par, uint32_t a) {
+    while (true) {
+        const uint32_t p = par[a] & 0xFFFFu;
+        if (p == a) return a;
+        a = p;
     }
 }
 __device__ __forceinline__ void lds_union(uint32_t *par, uint32_t a, uint32_t b) {
@@ -197,7 +251,12 @@ __device__ __forceinline__ uint32_t decode16_remote(const uint4 &v, uint32_t til
 // k_tile: bonds (Sec. 2.1), tile-local clusters (Sec. 2.3), new spins of
 // tile-interior clusters (Sec. 2.4), measurement of the incoming
 // configuration (Sec. 2.5).  One workgroup per TW x TW tile, 16 sites per
-// thread (one 16-site segment of a row).
+// thread (one 16-site segment of a row), so per-row bond and run data are
+// bit masks and most per-site work is one bit operation per 16 sites.
+// Cluster formation: every site's LDS word first points at the start of its
+// row run; vertical bonds (one per group that joins the same two runs) are
+// unions of run starts; each run start is then pointed at its root, which
+// collects the cluster size and, after numbering, the output byte.
 // =====================================================================
 template <int TW>
 __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
@@ -208,6 +267,9 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     constexpr int NW = NS / 32;
     constexpr int NWAVE = (NT + 63) / 64;
 
+    // per site: low 16 bits parent; high 16 bits cluster size (roots), then
+    // the root's output byte
+    __shared__ uint32_t s_par[NS];
     __shared__ Row s_up[TW + 1];
     __shared__ Row s_eb[TW];
     __shared__ Row s_nb[TW];
@@ -215,8 +277,6 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     __shared__ Row s_xn;
     __shared__ uint32_t s_eup[(TW + 31) / 32];
     __shared__ uint32_t s_xe[(TW + 31) / 32];
-    __shared__ uint32_t s_par[NS];
-    __shared__ uint32_t s_sz[NS / 2];
     __shared__ uint32_t s_bf[NW];
     __shared__ uint32_t s_pf[NW];
     __shared__ int8_t s_tab[256];
@@ -270,7 +330,6 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
             s_fb[tid] = q == 0 ? w0 : q == 1 ? w1 : q == 2 ? w2 : w3;
         }
     }
-    for (uint32_t i = tid; i < (uint32_t)(NS / 2); i += NT) s_sz[i] = 0u;
     for (uint32_t i = tid; i < (uint32_t)NW; i += NT) s_bf[i] = 0u;
     if (tid < (uint32_t)((TW + 31) / 32)) {
         s_eup[tid] = 0u;
@@ -293,17 +352,18 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     __syncthreads();
 
     // ---- bonds (Sec. 2.1) and energy / magnetisation of the incoming spins
-    const Row rowv = s_up[ly];
-    const uint32_t upN = (uint32_t)(s_up[ly + 1] >> x0) & 0xFFFFu;
-    const uint32_t ebit = (s_eup[ly >> 5] >> (ly & 31u)) & 1u;
-    const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
-    const uint32_t upE = (up >> 1) | (nxt << 15);
-    const uint32_t eqE = ~(up ^ upE) & 0xFFFFu;
-    const uint32_t eqN = ~(up ^ upN) & 0xFFFFu;
-    int32_t e_part = 2 * (__popc(eqE) + __popc(eqN)) - 32;
-    int32_t m_part = 2 * __popc(up) - 16;
-    uint32_t rE = 0u, rN = 0u;
+    int32_t e_part, m_part;
     {
+        const Row rowv = s_up[ly];
+        const uint32_t upN = (uint32_t)(s_up[ly + 1] >> x0) & 0xFFFFu;
+        const uint32_t ebit = (s_eup[ly >> 5] >> (ly & 31u)) & 1u;
+        const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
+        const uint32_t upE = (up >> 1) | (nxt << 15);
+        const uint32_t eqE = ~(up ^ upE) & 0xFFFFu;
+        const uint32_t eqN = ~(up ^ upN) & 0xFFFFu;
+        e_part = 2 * (__popc(eqE) + __popc(eqN)) - 32;
+        m_part = 2 * __popc(up) - 16;
+        uint32_t rE = 0u, rN = 0u;
         const uint32_t c0 = (gy * L + gx0) >> 1;
         const uint32_t T = d.T;
 #pragma unroll
@@ -313,31 +373,38 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
             rE |= ((uint32_t)(w0 < T) << (2 * j)) | ((uint32_t)(w2 < T) << (2 * j + 1));
             rN |= ((uint32_t)(w1 < T) << (2 * j)) | ((uint32_t)(w3 < T) << (2 * j + 1));
         }
+        uint32_t bE = eqE & rE, bN = eqN & rN;
+        if (seg == RPT - 1) {
+            if (bE >> 15) atomicOr(&s_xe[ly >> 5], 1u << (ly & 31u));
+            bE &= 0x7FFFu;
+        }
+        if (ly == TW - 1) {
+            reinterpret_cast<uint16_t *>(&s_xn)[seg] = (uint16_t)bN;
+            bN = 0u;
+        }
+        reinterpret_cast<uint16_t *>(s_eb)[ly * RPT + seg] = (uint16_t)bE;
+        reinterpret_cast<uint16_t *>(s_nb)[ly * RPT + seg] = (uint16_t)bN;
     }
-    uint32_t bE = eqE & rE, bN = eqN & rN;
-    if (seg == RPT - 1) {
-        if (bE >> 15) atomicOr(&s_xe[ly >> 5], 1u << (ly & 31u));
-        bE &= 0x7FFFu;
-    }
-    if (ly == TW - 1) {
-        reinterpret_cast<uint16_t *>(&s_xn)[seg] = (uint16_t)bN;
-        bN = 0u;
-    }
-    reinterpret_cast<uint16_t *>(s_eb)[ly * RPT + seg] = (uint16_t)bE;
-    reinterpret_cast<uint16_t *>(s_nb)[ly * RPT + seg] = (uint16_t)bN;
     __syncthreads();
 
-    // ---- row runs: a site starts a run unless bonded to its west neighbour
+    // ---- row runs: every site points at the start of its run
     const Row E0 = s_eb[ly];
     const Row B0 = (Row)~(Row)(E0 << 1);
     const uint32_t st = (uint32_t)(B0 >> x0) & 0xFFFFu;
+    const uint32_t rs0 = rowbase + hsb_le(B0, x0);
     {
-        uint32_t m = st;
-        while (m) {
-            const uint32_t i = (uint32_t)__ffs((int)m) - 1u;
-            m &= m - 1u;
-            s_par[rowbase + x0 + i] = rowbase + x0 + i;
+        uint32_t rs[16];
+        uint32_t cur = rs0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if ((st >> q) & 1u) cur = rowbase + x0 + (uint32_t)q;
+            rs[q] = cur;
         }
+        uint4 *dst = reinterpret_cast<uint4 *>(&s_par[rowbase + x0]);
+        dst[0] = make_uint4(rs[0], rs[1], rs[2], rs[3]);
+        dst[1] = make_uint4(rs[4], rs[5], rs[6], rs[7]);
+        dst[2] = make_uint4(rs[8], rs[9], rs[10], rs[11]);
+        dst[3] = make_uint4(rs[12], rs[13], rs[14], rs[15]);
     }
     __syncthreads();
 
@@ -346,50 +413,36 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     if (ly + 1u < (uint32_t)TW) {
         const Row V = s_nb[ly];
         const Row E1 = s_eb[ly + 1];
-        const Row B1 = (Row)~(Row)(E1 << 1);
         const Row R = V & (Row)~(Row)((V << 1) & (E0 << 1) & (E1 << 1));
         uint32_t r = (uint32_t)(R >> x0) & 0xFFFFu;
         while (r) {
             const uint32_t i = (uint32_t)__ffs((int)r) - 1u;
             r &= r - 1u;
-            const uint32_t x = x0 + i;
-            lds_union(s_par, rowbase + hsb_le(B0, x), rowbase + TW + hsb_le(B1, x));
-        }
-    }
-    __syncthreads();
-    {
-        uint32_t m = st;
-        while (m) {
-            const uint32_t i = (uint32_t)__ffs((int)m) - 1u;
-            m &= m - 1u;
-            const uint32_t s = rowbase + x0 + i;
-            atomicMin(&s_par[s], lds_find(s_par, s));
+            lds_union2(s_par, rowbase + x0 + i, rowbase + TW + x0 + i);
         }
     }
     __syncthreads();
 
-    // ---- cluster sizes and boundary flags, one piece (run fragment) at a time
-    const uint32_t rs0 = hsb_le(B0, x0);
+    // ---- every run start to its root; cluster sizes; clusters that touch
+    // the tile edge
+    uint32_t rootmask = 0u;
     {
-        uint32_t pm = st | 1u;
-        uint32_t prev_root = kEmpty, acc = 0u;
         const bool edge_row = (ly == 0u) || (ly == (uint32_t)TW - 1u);
-        while (pm) {
-            const uint32_t i = (uint32_t)__ffs((int)pm) - 1u;
-            pm &= pm - 1u;
-            const uint32_t j = pm ? (uint32_t)__ffs((int)pm) - 1u : 16u;
-            const uint32_t rs = (i == 0u) ? rs0 : x0 + i;
-            const uint32_t root = s_par[rowbase + rs];
-            if (root != prev_root) {
-                if (acc) atomicAdd(&s_sz[prev_root >> 1], acc << (16u * (prev_root & 1u)));
-                prev_root = root;
-                acc = 0u;
-            }
-            acc += j - i;
-            const bool flag = edge_row || (i == 0u && seg == 0u) || (j == 16u && seg == RPT - 1u);
-            if (flag) atomicOr(&s_bf[root >> 5], 1u << (root & 31u));
+        uint32_t m = st;
+        while (m) {
+            const uint32_t i = (uint32_t)__ffs((int)m) - 1u;
+            m &= m - 1u;
+            const uint32_t n = rowbase + x0 + i;
+            const uint32_t root = lds_root(s_par, n);
+            if (root != n)
+                atomicMin(&s_par[n], root);
+            else
+                rootmask |= 1u << i;
+            const uint32_t len = run_len_row<Row>(B0, x0 + i);
+            atomicAdd(&s_par[root], len << 16);
+            if (edge_row || x0 + i == 0u || x0 + i + len == (uint32_t)TW)
+                atomicOr(&s_bf[root >> 5], 1u << (root & 31u));
         }
-        if (acc) atomicAdd(&s_sz[prev_root >> 1], acc << (16u * (prev_root & 1u)));
     }
     __syncthreads();
 
@@ -421,36 +474,60 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     }
     __syncthreads();
 
+    // ---- roots: node tables out, output byte into the root's word,
+    // interior-cluster statistics in
+    uint32_t n_int = 0u, max_int = 0u, sq_int = 0u;
+    while (rootmask) {
+        const uint32_t q = (uint32_t)__ffs((int)rootmask) - 1u;
+        rootmask &= rootmask - 1u;
+        const uint32_t root = rowbase + x0 + q;
+        const uint32_t S = s_par[root] >> 16;
+        const uint32_t w = s_bf[root >> 5];
+        const uint32_t bit = 1u << (root & 31u);
+        uint32_t code;
+        if (w & bit) {
+            const uint32_t k = s_pf[root >> 5] + __popc(w & (bit - 1u));
+            const uint32_t node = tile * kNodeSlots + k;
+            d.key[node] = gy * L + gx0 + q;
+            d.nsize[node] = S;
+            par_cur[node] = node;
+            code = 2u + k;
+        } else {
+            code = ((uint32_t)(s_fb[ly] >> (x0 + q)) & 1u) ? 0xFFu : 0x01u;
+            ++n_int;
+            max_int = max(max_int, S);
+            sq_int += S * S;
+            atomicAdd(&s_hist[31 - __clz((int)max(S, 1u))], 1u);
+            if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
+        }
+        s_par[root] = root | (code << 16);
+    }
+    __syncthreads();
+
     // ---- outputs: one byte per site (final spin or node code)
     uint32_t out[4] = {0u, 0u, 0u, 0u};
-    uint32_t lab[16];
-    uint32_t rootmask = 0u;
     {
-        uint32_t cur_root = 0u, cur_byte = 0u, cur_lab = 0u;
+        uint32_t cur = rs0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            if (q == 0 || ((st >> q) & 1u)) {
-                const uint32_t rs = (q == 0) ? rs0 : x0 + (uint32_t)q;
-                cur_root = s_par[rowbase + rs];
-                const uint32_t w = s_bf[cur_root >> 5];
-                const uint32_t bit = 1u << (cur_root & 31u);
-                if (w & bit) {
-                    const uint32_t k = s_pf[cur_root >> 5] + __popc(w & (bit - 1u));
-                    cur_byte = 2u + k;
-                    cur_lab = 0x80000000u | (tile * kNodeSlots + k);
-                } else {
-                    const uint32_t f = (uint32_t)(s_fb[cur_root / TW] >> (cur_root % TW)) & 1u;
-                    cur_byte = f ? 0xFFu : 0x01u;
-                    cur_lab = (ty * TW + cur_root / TW) * L + tx * TW + cur_root % TW;
-                }
-                if (cur_root == rowbase + x0 + (uint32_t)q) rootmask |= 1u << q;
-            }
-            out[q >> 2] |= cur_byte << (8 * (q & 3));
-            lab[q] = cur_lab;
+            if ((st >> q) & 1u) cur = rowbase + x0 + (uint32_t)q;
+            const uint32_t root = s_par[cur] & 0xFFFFu;
+            const uint32_t code = s_par[root] >> 16;
+            out[q >> 2] |= code << (8 * (q & 3));
         }
     }
     *reinterpret_cast<uint4 *>(sout + (size_t)gy * L + gx0) = make_uint4(out[0], out[1], out[2], out[3]);
     if (d.labels) {
+        uint32_t lab[16];
+        uint32_t cur = rs0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if ((st >> q) & 1u) cur = rowbase + x0 + (uint32_t)q;
+            const uint32_t root = s_par[cur] & 0xFFFFu;
+            const uint32_t code = (out[q >> 2] >> (8 * (q & 3))) & 0xFFu;
+            lab[q] = (code >= 2u && code < 254u) ? (0x80000000u | (tile * kNodeSlots + code - 2u))
+                                                 : (ty * TW + root / TW) * L + tx * TW + root % TW;
+        }
         uint4 *lp = reinterpret_cast<uint4 *>(d.labels + (size_t)gy * L + gx0);
         lp[0] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
         lp[1] = make_uint4(lab[4], lab[5], lab[6], lab[7]);
@@ -468,30 +545,6 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
         if (ly == (uint32_t)TW - 1u)
             *reinterpret_cast<uint4 *>(eg + 3 * TW + x0) =
                 make_uint4(out[0] - 0x02020202u, out[1] - 0x02020202u, out[2] - 0x02020202u, out[3] - 0x02020202u);
-    }
-
-    // ---- cluster roots in this segment: nodes out, interior statistics in
-    uint32_t n_int = 0u, max_int = 0u, sq_int = 0u;
-    while (rootmask) {
-        const uint32_t q = (uint32_t)__ffs((int)rootmask) - 1u;
-        rootmask &= rootmask - 1u;
-        const uint32_t root = rowbase + x0 + q;
-        const uint32_t S = (s_sz[root >> 1] >> (16u * (root & 1u))) & 0xFFFFu;
-        const uint32_t w = s_bf[root >> 5];
-        const uint32_t bit = 1u << (root & 31u);
-        if (w & bit) {
-            const uint32_t k = s_pf[root >> 5] + __popc(w & (bit - 1u));
-            const uint32_t node = tile * kNodeSlots + k;
-            d.key[node] = gy * L + gx0 + q;
-            d.nsize[node] = S;
-            par_cur[node] = node;
-        } else {
-            ++n_int;
-            max_int = max(max_int, S);
-            sq_int += S * S;
-            atomicAdd(&s_hist[31 - __clz((int)max(S, 1u))], 1u);
-            if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
-        }
     }
 
     // ---- workgroup reductions -> tile partial

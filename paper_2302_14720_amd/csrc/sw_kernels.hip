@@ -94,26 +94,19 @@ __device__ __forceinline__ uint32_t lds_find(uint32_t *par, uint32_t a) {
         a = gp;
     }
 }
-// Union of the sets of a and b.  Both finds advance together (their LDS
-// loads overlap) and halve their paths with min-updates; the larger root is
-// then linked under the smaller one by compare-and-swap, retrying if another
-// lane linked it first.
+// Union of the sets of a and b.  Both finds advance together, so their LDS
+// loads overlap; the larger root is then linked under the smaller one by
+// compare-and-swap, retrying if another lane linked it first.  No path
+// compression here: the pass after the unions points every run start at its
+// root.
 __device__ __forceinline__ void lds_union2(uint32_t *par, uint32_t a, uint32_t b) {
     while (true) {
-        while (true) {
-            const uint32_t pa = lds_load(&par[a]), pb = lds_load(&par[b]);
-            const bool ra = pa == a, rb = pb == b;
-            if (ra && rb) break;
-            if (!ra) {
-                const uint32_t ga = lds_load(&par[pa]);
-                if (ga != pa) atomicMin(&par[a], ga);
-                a = ga;
-            }
-            if (!rb) {
-                const uint32_t gb = lds_load(&par[pb]);
-                if (gb != pb) atomicMin(&par[b], gb);
-                b = gb;
-            }
+        uint32_t pa = lds_load(&par[a]), pb = lds_load(&par[b]);
+        while (pa != a || pb != b) {
+            a = pa;
+            b = pb;
+            pa = lds_load(&par[a]);
+            pb = lds_load(&par[b]);
         }
         if (a == b) return;
         const uint32_t hi = max(a, b), lo = min(a, b);
@@ -271,8 +264,9 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     // the root's output byte
     __shared__ uint32_t s_par[NS];
     __shared__ Row s_up[TW + 1];
-    __shared__ Row s_eb[TW];
-    __shared__ Row s_nb[TW];
+    __shared__ Row s_ebnb[2 * TW];  // bond masks to E (rows 0..TW-1) and N (rows TW..2TW-1)
+    Row *const s_eb = s_ebnb;
+    Row *const s_nb = s_ebnb + TW;
     __shared__ Row s_fb[TW];
     __shared__ Row s_xn;
     __shared__ uint32_t s_eup[(TW + 31) / 32];
@@ -281,7 +275,11 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     __shared__ uint32_t s_pf[NW];
     __shared__ int8_t s_tab[256];
     __shared__ uint32_t s_hist[12];
-    __shared__ int32_t s_red[NWAVE][5];
+    // root | size << 16 of each node; for 64-wide tiles it reuses the bond
+    // masks, which are dead once the unions are done
+    __shared__ uint32_t s_node_own[TW == 64 ? 1 : 4 * TW];
+    uint32_t *const s_node = TW == 64 ? reinterpret_cast<uint32_t *>(s_ebnb) : s_node_own;
+    __shared__ int32_t s_red[NWAVE][8];
     __shared__ uint32_t s_k;
 
     const uint32_t tid = threadIdx.x;
@@ -474,9 +472,9 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     }
     __syncthreads();
 
-    // ---- roots: node tables out, output byte into the root's word,
-    // interior-cluster statistics in
-    uint32_t n_int = 0u, max_int = 0u, sq_int = 0u;
+    // ---- roots: output byte into the root's word; node entries staged in
+    // LDS; interior-cluster statistics (bins 0-2 in registers)
+    uint32_t n_int = 0u, max_int = 0u, sq_int = 0u, h0 = 0u, h1 = 0u, h2 = 0u;
     while (rootmask) {
         const uint32_t q = (uint32_t)__ffs((int)rootmask) - 1u;
         rootmask &= rootmask - 1u;
@@ -487,22 +485,33 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
         uint32_t code;
         if (w & bit) {
             const uint32_t k = s_pf[root >> 5] + __popc(w & (bit - 1u));
-            const uint32_t node = tile * kNodeSlots + k;
-            d.key[node] = gy * L + gx0 + q;
-            d.nsize[node] = S;
-            par_cur[node] = node;
+            s_node[k] = root | (S << 16);
             code = 2u + k;
         } else {
             code = ((uint32_t)(s_fb[ly] >> (x0 + q)) & 1u) ? 0xFFu : 0x01u;
             ++n_int;
             max_int = max(max_int, S);
             sq_int += S * S;
-            atomicAdd(&s_hist[31 - __clz((int)max(S, 1u))], 1u);
+            if (S == 1u)
+                ++h0;
+            else if (S < 4u)
+                ++h1;
+            else if (S < 8u)
+                ++h2;
+            else
+                atomicAdd(&s_hist[31 - __clz((int)S)], 1u);
             if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
         }
         s_par[root] = root | (code << 16);
     }
     __syncthreads();
+    // node tables of this tile, written in node order
+    for (uint32_t k = tid; k < s_k; k += NT) {
+        const uint32_t e = s_node[k], root = e & 0xFFFFu, node = tile * kNodeSlots + k;
+        d.key[node] = (ty * TW + root / TW) * L + tx * TW + root % TW;
+        d.nsize[node] = e >> 16;
+        par_cur[node] = node;
+    }
 
     // ---- outputs: one byte per site (final spin or node code)
     uint32_t out[4] = {0u, 0u, 0u, 0u};
@@ -555,6 +564,9 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
         n_int += __shfl_xor(n_int, o, 64);
         max_int = max(max_int, (uint32_t)__shfl_xor((int)max_int, o, 64));
         sq_int += __shfl_xor(sq_int, o, 64);
+        h0 += __shfl_xor(h0, o, 64);
+        h1 += __shfl_xor(h1, o, 64);
+        h2 += __shfl_xor(h2, o, 64);
     }
     if ((tid & 63u) == 0u) {
         s_red[tid >> 6][0] = e_part;
@@ -562,16 +574,22 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
         s_red[tid >> 6][2] = (int32_t)n_int;
         s_red[tid >> 6][3] = (int32_t)max_int;
         s_red[tid >> 6][4] = (int32_t)sq_int;
+        s_red[tid >> 6][5] = (int32_t)h0;
+        s_red[tid >> 6][6] = (int32_t)h1;
+        s_red[tid >> 6][7] = (int32_t)h2;
     }
     __syncthreads();
     if (tid == 0u) {
-        int32_t e = 0, m = 0, n = 0, mx = 0, sq = 0;
+        int32_t e = 0, m = 0, n = 0, mx = 0, sq = 0, b0 = 0, b1 = 0, b2 = 0;
         for (int w = 0; w < NWAVE; ++w) {
             e += s_red[w][0];
             m += s_red[w][1];
             n += s_red[w][2];
             mx = max(mx, s_red[w][3]);
             sq += s_red[w][4];
+            b0 += s_red[w][5];
+            b1 += s_red[w][6];
+            b2 += s_red[w][7];
         }
         int32_t *tp = d.tpart + (size_t)tile * kTilePart;
         tp[TP_E] = e;
@@ -579,7 +597,10 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
         tp[TP_N] = n;
         tp[TP_MAX] = mx;
         tp[TP_SQ] = sq;
-        for (int b = 0; b < 12; ++b) tp[TP_HIST + b] = (int32_t)s_hist[b];
+        tp[TP_HIST + 0] = b0;
+        tp[TP_HIST + 1] = b1;
+        tp[TP_HIST + 2] = b2;
+        for (int b = 3; b < 12; ++b) tp[TP_HIST + b] = (int32_t)s_hist[b];
         d.nk[pc][tile] = s_k;
         uint64_t xe = s_xe[0];
         if constexpr (TW == 64) xe |= (uint64_t)s_xe[1] << 32;

@@ -48,41 +48,75 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def _bind(l: ctypes.CDLL) -> ctypes.CDLL:
+    P = ctypes.c_void_p
+    i32, u32, u64, i64, f64 = (ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
+                               ctypes.c_int64, ctypes.c_double)
+    l.orc_philox4x32_10.argtypes = [P, P, P]
+    l.orc_philox4x32_10.restype = None
+    l.orc_threshold.argtypes = [f64, f64]
+    l.orc_threshold.restype = u32
+    l.orc_init.argtypes = [i32, u64, i32, P]
+    l.orc_init.restype = None
+    l.orc_bonds.argtypes = [i32, u32, u64, u32, P, P]
+    l.orc_bonds.restype = None
+    l.orc_label.argtypes = [i32, P, P]
+    l.orc_label.restype = None
+    l.orc_flip_spin.argtypes = [u64, u32, u32]
+    l.orc_flip_spin.restype = i32
+    l.orc_assign.argtypes = [i32, u64, u32, P, P]
+    l.orc_assign.restype = None
+    l.orc_observe.argtypes = [i32, f64, u64, P, P, P, P]
+    l.orc_observe.restype = None
+    l.orc_sweep.argtypes = [i32, f64, u32, u64, u32, P, P, P, P, P]
+    l.orc_sweep.restype = ctypes.c_int
+    l.orc_run.argtypes = [i32, f64, u32, u64, u32, i64, P, P]
+    l.orc_run.restype = ctypes.c_int
+    l.orc_chains.argtypes = [i32, f64, u32, u64, i64, i32, P, P]
+    l.orc_chains.restype = ctypes.c_int
+    l.orc_one_step_codes.argtypes = [i32, u32, u64, i64, u32, P, P]
+    l.orc_one_step_codes.restype = ctypes.c_int
+    return l
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        l = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        i32, u32, u64, i64, f64 = (ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
-                                   ctypes.c_int64, ctypes.c_double)
-        l.orc_philox4x32_10.argtypes = [P, P, P]
-        l.orc_philox4x32_10.restype = None
-        l.orc_threshold.argtypes = [f64, f64]
-        l.orc_threshold.restype = u32
-        l.orc_init.argtypes = [i32, u64, i32, P]
-        l.orc_init.restype = None
-        l.orc_bonds.argtypes = [i32, u32, u64, u32, P, P]
-        l.orc_bonds.restype = None
-        l.orc_label.argtypes = [i32, P, P]
-        l.orc_label.restype = None
-        l.orc_flip_spin.argtypes = [u64, u32, u32]
-        l.orc_flip_spin.restype = i32
-        l.orc_assign.argtypes = [i32, u64, u32, P, P]
-        l.orc_assign.restype = None
-        l.orc_observe.argtypes = [i32, f64, u64, P, P, P, P]
-        l.orc_observe.restype = None
-        l.orc_sweep.argtypes = [i32, f64, u32, u64, u32, P, P, P, P, P]
-        l.orc_sweep.restype = ctypes.c_int
-        l.orc_run.argtypes = [i32, f64, u32, u64, u32, i64, P, P]
-        l.orc_run.restype = ctypes.c_int
-        l.orc_chains.argtypes = [i32, f64, u32, u64, i64, i32, P, P]
-        l.orc_chains.restype = ctypes.c_int
-        l.orc_one_step_codes.argtypes = [i32, u32, u64, i64, u32, P, P]
-        l.orc_one_step_codes.restype = ctypes.c_int
-        _lib = l
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
+
+
+class using:
+    """Context manager that routes every call of this module to another
+    build of the oracle (used by the tests that plant mistakes in a copy of
+    sw_oracle.c and check that the pins catch them)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        _lib = _bind(ctypes.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+
+
+def build_variant(source: str, out_dir: str, name: str) -> str:
+    """Compiles C source text (a modified copy of sw_oracle.c) to a shared
+    library in out_dir and returns its path."""
+    src = os.path.join(out_dir, name + ".c")
+    with open(src, "w") as f:
+        f.write(source)
+    so = os.path.join(out_dir, name + ".so")
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-I" + _HERE,
+                           "-o", so, src, "-lm"])
+    return so
 
 
 def _p(a: np.ndarray):

@@ -1,0 +1,59 @@
+"""Planted mistakes in a copy of the oracle must fail at least one pin.
+
+Each case rewrites one line of sw_oracle.c the way a plausible bug would
+(a wrong neighbour, a dropped factor, an off-by-one, a swapped word, ...),
+builds the copy, routes the oracle module to it and runs the pins named
+for that case; the test passes only if some pin rejects the mutant.
+"""
+import os
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "sw_oracle.c")
+BETA_C = pins.BETA_C
+
+MUTANTS = [
+    ("bond uses <=", "&& wE < T) b |= 1u;", "&& wE <= T) b |= 1u;",
+     [pins.test_bond_threshold_is_strict]),
+    ("north neighbour is south", "return ((y + 1u) % L) * L + x;", "return ((y + L - 1u) % L) * L + x;",
+     [lambda: pins.test_bond_keying_and_rule(6)]),
+    ("bond word index", "uint32_t wN = r[2u * (s & 1u) + 1u];", "uint32_t wN = r[(s & 1u) + 1u];",
+     [lambda: pins.test_bond_keying_and_rule(6)]),
+    ("dropped factor 2 in p", "double p = -expm1(-2.0 * beta * J);", "double p = -expm1(-beta * J);",
+     [pins.test_threshold_closed_form_at_beta_c, pins.test_4x4_exact_enumeration_chi2]),
+    ("flip always word 0", "uint32_t bit = (r[(root >> 5) & 3u] >> (root & 31u)) & 1u;",
+     "uint32_t bit = (r[0] >> (root & 31u)) & 1u;", [pins.test_assignment_uses_root_flip_bit]),
+    ("labels keep the larger root", "if (ra < rb) parent[rb] = ra;", "if (ra > rb) parent[rb] = ra;",
+     [lambda: pins.test_labels_equal_bfs(8)]),
+    ("energy drops the N edges", "        e += si * spins[north_of(s, (uint32_t)L)];\n", "",
+     [pins.test_records_and_invariants, pins.test_energy_at_beta_c_L64_matches_ferdinand_fisher]),
+    ("cluster flips instead of being assigned", "spins[s] = (int8_t)orc_flip_spin(seed, t, labels[s]);",
+     "spins[s] = (int8_t)(spins[s] * orc_flip_spin(seed, t, labels[s]));",
+     [pins.test_spin_reversal_symmetry]),
+    ("log2 bin off by one", "while ((sz >> (k + 1)) != 0u) ++k;", "while ((sz >> k) != 0u && k < 32) ++k;",
+     [pins.test_records_and_invariants]),
+    ("Philox multipliers swapped", "uint64_t prod_a = (uint64_t)0xD2511F53u * (uint64_t)x0;",
+     "uint64_t prod_a = (uint64_t)0xCD9E8D57u * (uint64_t)x0;", [pins.test_philox_known_answers]),
+    ("hot start inverted", "spins[s] = (r[0] & 1u) ? (int8_t)-1 : (int8_t)1;",
+     "spins[s] = (r[0] & 1u) ? (int8_t)1 : (int8_t)-1;", [pins.test_init_hot_and_cold]),
+    ("bond ignores the spins", "if (spins[s] == spins[east_of(s, (uint32_t)L)] && wE < T)", "if (wE < T)",
+     [lambda: pins.test_bond_keying_and_rule(5), pins.test_4x4_exact_enumeration_chi2]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,checks", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(name, old, new, checks, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not found once: {old!r}"
+    so = oracle.build_variant(src.replace(old, new), str(tmp_path), "mutant")
+    caught = []
+    with oracle.using(so):
+        for check in checks:
+            try:
+                check()
+            except AssertionError:
+                caught.append(check)
+    assert caught, f"no pin caught the mutant '{name}'"

@@ -88,6 +88,16 @@ def test_bond_keying_and_rule(L):
             assert bool((b[s] >> d) & 1) == want, (s, d)
 
 
+def test_bond_threshold_is_strict():
+    """An edge whose word equals T is not bonded; with T + 1 it is."""
+    L, seed, t = 4, 2718, 9
+    spins = np.ones(L * L, dtype=np.int8)
+    for s_, d in ((5, 0), (6, 1), (11, 0)):
+        w = exact.bond_word(seed, t, s_, d)
+        assert not (oracle.bonds(L, w, seed, t, spins)[s_] >> d) & 1
+        assert (oracle.bonds(L, w + 1, seed, t, spins)[s_] >> d) & 1
+
+
 def test_cold_start_first_bonds_are_the_uniform_test():
     L, seed = 16, 99
     T = oracle.threshold(BETA_C)

@@ -81,6 +81,60 @@ def cpu_baseline(L: int, seed: int):
     }
 
 
+def batched_vs_plain(args):
+    """The 256-replica temperature grid swept as one batch (five launches per
+    sweep for all replicas) and as 256 plain sims (one sw_sweep per replica
+    per sweep, as a caller without batching would drive them)."""
+    import torch
+
+    import paper_2302_14720_amd as sw
+    from paper_2302_14720_amd.replicas import grid_table
+
+    L, beta, seed = grid_table(256, 1000)
+    sites = int((L.astype("int64") ** 2).sum())
+    print(f"[bench] batched: {len(L)} replicas, {sites} sites", file=sys.stderr, flush=True)
+    b = sw.Batch(L, beta, 1.0, seed)
+    b.sweep(args.warmup)
+    b.sync()
+    t0 = time.perf_counter()
+    b.sweep(args.batch_steps)
+    b.sync()
+    bdt = time.perf_counter() - t0
+    recs = b.observables()
+    assert int(recs["sweep"][0]) == args.warmup + args.batch_steps - 1
+    b.close()
+    print(f"[bench] batched: {bdt * 1e3:.2f} ms for {args.batch_steps} sweeps", file=sys.stderr, flush=True)
+
+    sims = [sw.Sim(int(L[r]), float(beta[r]), 1.0, int(seed[r])) for r in range(len(L))]
+    for s_ in sims:
+        s_.sweep(2)
+    for s_ in sims:
+        s_.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.plain_steps):
+        for s_ in sims:
+            s_.sweep(1)
+    for s_ in sims:
+        s_.sync()
+    pdt = time.perf_counter() - t0
+    for s_ in sims:
+        s_.close()
+    print(f"[bench] plain: {pdt * 1e3:.2f} ms for {args.plain_steps} sweeps", file=sys.stderr, flush=True)
+    bval = sites * args.batch_steps / bdt
+    pval = sites * args.plain_steps / pdt
+    return {
+        "workload": "256 replicas, L = {64,128,256,512,1024}[r mod 5], beta_k = 0.40 + 0.08 k/31 "
+                    "(k = r // 8), seed 1000 + r, hot start, J = 1",
+        "replicas": len(L), "sites": sites,
+        "value": bval, "unit": "site-updates/s", "sweeps": args.batch_steps,
+        "ms_per_step": bdt * 1e3 / args.batch_steps,
+        "plain_value": pval, "plain_sweeps": args.plain_steps,
+        "plain_ms_per_step": pdt * 1e3 / args.plain_steps,
+        "batched_over_plain": bval / pval,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +147,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-kernel profile and the cold-start leg (for counter runs)")
+    ap.add_argument("--batch-steps", type=int, default=200,
+                    help="timed sweeps of the 256-replica batch")
+    ap.add_argument("--plain-steps", type=int, default=10,
+                    help="timed sweeps of the same replicas as plain sims, one sw_sweep per replica per sweep")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for "
                          "HBM byte counters)")
@@ -211,7 +270,7 @@ def main() -> int:
         "cold_start": {"sweeps": args.cold_sweeps, "value": N * args.cold_sweeps / cdt,
                        "ms_per_step": cdt * 1e3 / args.cold_sweeps,
                        "first_sweep_max_cluster": int(crec["max_cluster"])},
-        "batched": None,
+        "batched": None if args.no_batched else batched_vs_plain(args),
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on one L=%d sweep" % L, file=sys.stderr, flush=True)

@@ -186,6 +186,64 @@ void sw_destroy(sw_sim *sim);
 /* Message describing the last failure on this thread ("" if none). */
 const char *sw_last_error(void);
 
+/* ------------------------------------------------------------- batches
+ * A batch advances n independent lattices (replicas) together: every kernel
+ * of a sweep (Sec. 2) runs once over all replicas, so a sweep of the whole
+ * batch costs five kernel launches (replayed from one captured graph)
+ * instead of five per replica.  Replica r has its own L[r], beta[r], J[r],
+ * seed[r] and its own records; its spins, clusters and records are bit for
+ * bit those of a plain sim created with the same parameters and swept the
+ * same number of times.  All replicas share the sweep counter t.
+ * Limits: 1 <= n <= 4096; every L[r] as for sw_create (the tile is 64 when
+ * every L[r] is a multiple of 64, else 32); no labels or dense histogram. */
+typedef struct sw_batch sw_batch;
+
+/* Device bytes of a batch with these lattice sides and `ring` records per
+ * replica (0 = 1024); 0 when the arguments are invalid. */
+size_t sw_batch_workspace_bytes(int32_t n, const int32_t *L, int64_t ring);
+
+/* Creates a batch of n replicas, L/beta/J/seed being arrays of length n
+ * (host memory, read during the call), all started with `init`
+ * (SW_INIT_HOT / SW_INIT_COLD), t = 0.  dev_workspace: NULL (the library
+ * allocates) or a 256-byte-aligned device buffer of >= ws_bytes =
+ * sw_batch_workspace_bytes(...) bytes that the caller keeps alive until
+ * sw_batch_destroy.  hip_stream: the stream for all of the batch's work
+ * (NULL with dev_workspace NULL: the library creates one).  SW_EINVAL for a
+ * bad replica (the message names it), SW_ENOMEM for a small workspace. */
+int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const double *J,
+                    const uint64_t *seed, int32_t init, int64_t ring, void *dev_workspace,
+                    size_t ws_bytes, void *hip_stream, sw_batch **out);
+
+/* Re-initialises every replica (SW_INIT_HOT / SW_INIT_COLD) and sets t = 0. */
+int sw_batch_reset(sw_batch *batch, int32_t init_mode);
+
+/* Enqueues n >= 0 sweeps of every replica and returns without waiting. */
+int sw_batch_sweep(sw_batch *batch, int64_t n);
+
+/* Waits for all enqueued work of the batch. */
+int sw_batch_sync(sw_batch *batch);
+
+/* Records of the last completed sweep, one per replica, into out[0..n-1]
+ * (waits).  SW_ESTATE if no sweep has run since create / reset. */
+int sw_batch_observables(sw_batch *batch, sw_obs *out);
+
+/* Records first .. first+count-1 of replica r (as sw_series). */
+int sw_batch_series(sw_batch *batch, int32_t r, int64_t first, int64_t count, sw_obs *out);
+
+/* Current spins of replica r (n == L[r]^2), as sw_get_spins. */
+int sw_batch_get_spins(sw_batch *batch, int32_t r, int8_t *host, int64_t n);
+
+/* Number of replicas; index of the next sweep; side, bond threshold of
+ * replica r (0 for a bad index); tile side used. */
+int32_t sw_batch_size(const sw_batch *batch);
+int64_t sw_batch_next_sweep(const sw_batch *batch);
+int32_t sw_batch_lattice(const sw_batch *batch, int32_t r);
+uint32_t sw_batch_threshold(const sw_batch *batch, int32_t r);
+int32_t sw_batch_tile(const sw_batch *batch);
+
+/* Destroys the batch (waits for its stream first); NULL is a no-op. */
+void sw_batch_destroy(sw_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

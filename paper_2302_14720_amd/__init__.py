@@ -83,6 +83,21 @@ _SIGNATURES = {
     "sw_tile": (ctypes.c_int32, [_P]),
     "sw_destroy": (None, [_P]),
     "sw_last_error": (ctypes.c_char_p, []),
+    "sw_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, _P, ctypes.c_int64]),
+    "sw_batch_create": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64,
+                                       _P, ctypes.c_size_t, _P, _P]),
+    "sw_batch_reset": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sw_batch_sweep": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "sw_batch_sync": (ctypes.c_int, [_P]),
+    "sw_batch_observables": (ctypes.c_int, [_P, _P]),
+    "sw_batch_series": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _P]),
+    "sw_batch_get_spins": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64]),
+    "sw_batch_size": (ctypes.c_int32, [_P]),
+    "sw_batch_next_sweep": (ctypes.c_int64, [_P]),
+    "sw_batch_lattice": (ctypes.c_int32, [_P, ctypes.c_int32]),
+    "sw_batch_threshold": (ctypes.c_uint32, [_P, ctypes.c_int32]),
+    "sw_batch_tile": (ctypes.c_int32, [_P]),
+    "sw_batch_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -223,6 +238,68 @@ def sw_last_error() -> str:
     return lib().sw_last_error().decode()
 
 
+# ------------------------------------------------------------- batch calls
+def _replica_arrays(L, beta, J, seed):
+    n = len(L)
+    La = np.ascontiguousarray(L, dtype=np.int32)
+    ba = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, dtype=np.float64), (n,)))
+    Ja = np.ascontiguousarray(np.broadcast_to(np.asarray(J, dtype=np.float64), (n,)))
+    sa = np.ascontiguousarray(np.broadcast_to(np.asarray(seed, dtype=np.uint64), (n,)))
+    return n, La, ba, Ja, sa
+
+
+def sw_batch_workspace_bytes(L, ring: int = 0) -> int:
+    La = np.ascontiguousarray(L, dtype=np.int32)
+    return int(lib().sw_batch_workspace_bytes(La.size, _ptr(La), ring))
+
+
+def sw_batch_create(L, beta, J, seed, init: int = SW_INIT_HOT, ring: int = 0, ws_ptr: int = 0,
+                    ws_bytes: int = 0, stream_ptr: int = 0) -> int:
+    n, La, ba, Ja, sa = _replica_arrays(L, beta, J, seed)
+    h = ctypes.c_void_p()
+    _check(lib().sw_batch_create(n, _ptr(La), _ptr(ba), _ptr(Ja), _ptr(sa), init, ring, ws_ptr or None,
+                                 ws_bytes, stream_ptr or None, ctypes.byref(h)))
+    return h.value
+
+
+def sw_batch_reset(h: int, init_mode: int = SW_INIT_HOT) -> None:
+    _check(lib().sw_batch_reset(h, init_mode))
+
+
+def sw_batch_sweep(h: int, n: int) -> None:
+    _check(lib().sw_batch_sweep(h, n))
+
+
+def sw_batch_sync(h: int) -> None:
+    _check(lib().sw_batch_sync(h))
+
+
+def sw_batch_observables(h: int) -> np.ndarray:
+    out = np.zeros(int(lib().sw_batch_size(h)), dtype=OBS_DTYPE)
+    _check(lib().sw_batch_observables(h, _ptr(out)))
+    return out
+
+
+def sw_batch_series(h: int, r: int, first: int, count: int) -> np.ndarray:
+    out = np.zeros(count, dtype=OBS_DTYPE)
+    _check(lib().sw_batch_series(h, r, first, count, _ptr(out)))
+    return out
+
+
+def sw_batch_get_spins(h: int, r: int) -> np.ndarray:
+    L = int(lib().sw_batch_lattice(h, r))
+    if L == 0:
+        raise SwError(SW_ERANGE, "replica index out of range")
+    out = np.empty(L * L, dtype=np.int8)
+    _check(lib().sw_batch_get_spins(h, r, _ptr(out), out.size))
+    return out
+
+
+def sw_batch_destroy(h: int) -> None:
+    if h:
+        lib().sw_batch_destroy(h)
+
+
 # ------------------------------------------------------------------- wrapper
 class Sim:
     """One lattice on the current GPU; workspace and stream come from torch."""
@@ -293,6 +370,79 @@ class Sim:
         h, self.handle = getattr(self, "handle", None), None
         if h:
             sw_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Independent replicas swept together (one launch per kernel of a sweep
+    for the whole batch); workspace and stream come from torch.  L is a
+    sequence of lattice sides; beta, J and seed are scalars or sequences of
+    the same length."""
+
+    def __init__(self, L, beta, J=1.0, seed=0, *, init: int = SW_INIT_HOT, ring: int = 0, device=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("Batch needs a ROCm GPU (torch.cuda.is_available() is False)")
+        n, La, ba, Ja, sa = _replica_arrays(L, beta, J, seed)
+        self.L = La.tolist()
+        nbytes = sw_batch_workspace_bytes(La, ring)
+        if nbytes == 0:
+            self.handle = sw_batch_create(La, ba, Ja, sa, init, ring)  # raises with the reason
+        dev = torch.device("cuda" if device is None else device)
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self._stream = torch.cuda.Stream(device=dev)
+        torch.cuda.current_stream(dev).synchronize()
+        self.handle = sw_batch_create(La, ba, Ja, sa, init, ring, self._ws.data_ptr(), nbytes,
+                                      self._stream.cuda_stream)
+
+    def __len__(self) -> int:
+        return len(self.L)
+
+    def sweep(self, n: int) -> None:
+        sw_batch_sweep(self.handle, n)
+
+    def sync(self) -> None:
+        sw_batch_sync(self.handle)
+
+    def reset(self, init: int = SW_INIT_HOT) -> None:
+        sw_batch_reset(self.handle, init)
+
+    def observables(self) -> np.ndarray:
+        return sw_batch_observables(self.handle)
+
+    def series(self, r: int, first: int, count: int) -> np.ndarray:
+        return sw_batch_series(self.handle, r, first, count)
+
+    def spins(self, r: int) -> np.ndarray:
+        return sw_batch_get_spins(self.handle, r)
+
+    def threshold(self, r: int) -> int:
+        return int(lib().sw_batch_threshold(self.handle, r))
+
+    @property
+    def next_sweep(self) -> int:
+        return int(lib().sw_batch_next_sweep(self.handle))
+
+    @property
+    def tile(self) -> int:
+        return int(lib().sw_batch_tile(self.handle))
+
+    def close(self) -> None:
+        h, self.handle = getattr(self, "handle", None), None
+        if h:
+            sw_batch_destroy(h)
 
     def __del__(self):
         try:

@@ -111,6 +111,40 @@ Layout layout_of(const sw_config &c) {
     return o;
 }
 
+// The device view of one lattice whose buffers start at `base`.
+Dev make_dev(const sw_config &c, char *base, const Layout &lo) {
+    Dev d;
+    memset(&d, 0, sizeof(d));
+    d.L = (uint32_t)c.L;
+    d.tw = (uint32_t)resolve_tile(c);
+    d.ntx = d.L / d.tw;
+    d.ntiles = d.ntx * d.ntx;
+    d.ngroups = (d.ntiles + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
+    d.T = bond_threshold(c.beta, c.J);
+    d.seed_lo = (uint32_t)(c.seed & 0xFFFFFFFFu);
+    d.seed_hi = (uint32_t)(c.seed >> 32);
+    d.ring_cap = (uint32_t)c.ring;
+    d.J = c.J;
+    for (int i = 0; i < 2; ++i) {
+        d.spins[i] = (int8_t *)(base + lo.spins[i]);
+        d.parent[i] = (uint32_t *)(base + lo.parent[i]);
+        d.nk[i] = (uint32_t *)(base + lo.nk[i]);
+    }
+    d.key = (uint32_t *)(base + lo.key);
+    d.nsize = (uint32_t *)(base + lo.nsize);
+    d.rspin = (int8_t *)(base + lo.rspin);
+    d.edge = (uint8_t *)(base + lo.edge);
+    d.xb = (uint64_t *)(base + lo.xb);
+    d.tpart = (int32_t *)(base + lo.tpart);
+    d.gpart = (uint64_t *)(base + lo.gpart);
+    d.acc = (uint64_t *)(base + lo.acc);
+    d.tdev = (uint64_t *)(base + lo.tdev);
+    d.ring = (sw_obs *)(base + lo.ring);
+    d.labels = (c.flags & SW_FLAG_LABELS) ? (uint32_t *)(base + lo.labels) : nullptr;
+    d.dense = (c.flags & SW_FLAG_DENSE_HIST) ? (uint64_t *)(base + lo.dense) : nullptr;
+    return d;
+}
+
 }  // namespace
 
 struct sw_sim {
@@ -262,37 +296,8 @@ int sw_create_ex(const sw_config *cfg, void *dev_workspace, size_t ws_bytes, voi
             s->own_stream = true;
         }
     }
-    char *base = (char *)s->ws;
     const sw_config &c = s->cfg;
-    Dev &d = s->dev;
-    memset(&d, 0, sizeof(d));
-    d.L = (uint32_t)c.L;
-    d.tw = (uint32_t)resolve_tile(c);
-    d.ntx = d.L / d.tw;
-    d.ntiles = d.ntx * d.ntx;
-    d.ngroups = (d.ntiles + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
-    d.T = bond_threshold(c.beta, c.J);
-    d.seed_lo = (uint32_t)(c.seed & 0xFFFFFFFFu);
-    d.seed_hi = (uint32_t)(c.seed >> 32);
-    d.ring_cap = (uint32_t)c.ring;
-    d.J = c.J;
-    for (int i = 0; i < 2; ++i) {
-        d.spins[i] = (int8_t *)(base + lo.spins[i]);
-        d.parent[i] = (uint32_t *)(base + lo.parent[i]);
-        d.nk[i] = (uint32_t *)(base + lo.nk[i]);
-    }
-    d.key = (uint32_t *)(base + lo.key);
-    d.nsize = (uint32_t *)(base + lo.nsize);
-    d.rspin = (int8_t *)(base + lo.rspin);
-    d.edge = (uint8_t *)(base + lo.edge);
-    d.xb = (uint64_t *)(base + lo.xb);
-    d.tpart = (int32_t *)(base + lo.tpart);
-    d.gpart = (uint64_t *)(base + lo.gpart);
-    d.acc = (uint64_t *)(base + lo.acc);
-    d.tdev = (uint64_t *)(base + lo.tdev);
-    d.ring = (sw_obs *)(base + lo.ring);
-    d.labels = (c.flags & SW_FLAG_LABELS) ? (uint32_t *)(base + lo.labels) : nullptr;
-    d.dense = (c.flags & SW_FLAG_DENSE_HIST) ? (uint64_t *)(base + lo.dense) : nullptr;
+    s->dev = make_dev(c, (char *)s->ws, lo);
 
     // Everything starts at zero: no nodes in either parity, empty accumulators.
     e = hipMemsetAsync(s->ws, 0, lo.total, s->stream);
@@ -503,6 +508,358 @@ void sw_destroy(sw_sim *s) {
     if (s->own_ws && s->ws) (void)hipFree(s->ws);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
+}
+
+}  // extern "C"
+
+// ===================================================================== batches
+
+struct sw_batch {
+    std::vector<sw_config> cfg;
+    std::vector<Dev> dev;  // host copies of the replicas' device views
+    swmi::BatchDev bd;
+    hipStream_t stream;
+    bool own_stream;
+    void *ws;
+    size_t ws_bytes;
+    bool own_ws;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    bool graph_tried;
+    uint64_t next_sweep;
+    uint64_t first_valid;
+    int device;
+};
+
+namespace {
+
+constexpr int64_t kDefaultBatchRing = 1024;
+
+struct BatchPlan {
+    std::vector<sw_config> cfg;
+    std::vector<size_t> base;  // workspace offset of every replica
+    size_t devs, tmap, wmap, gmap, total;
+    uint32_t ntiles, nwmap, ngroups, tw;
+};
+
+// Validates the replica table and lays out the batch workspace: the
+// replicas' buffers one after another, then the Dev table and the maps.
+int plan_batch(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
+               int32_t init, int64_t ring, BatchPlan *p) {
+    if (n < 1 || n > swmi::kMaxReplicas)
+        return fail(SW_EINVAL, "the number of replicas must be in [1, " + std::to_string(swmi::kMaxReplicas) + "]");
+    if (!L || !beta || !J || !seed) return fail(SW_EINVAL, "replica arrays must not be NULL");
+    if (init != SW_INIT_HOT && init != SW_INIT_COLD) return fail(SW_EINVAL, "init must be SW_INIT_HOT or SW_INIT_COLD");
+    bool all64 = true;
+    for (int32_t r = 0; r < n; ++r) all64 = all64 && (L[r] % 64 == 0);
+    p->tw = all64 ? 64u : 32u;
+    p->cfg.assign((size_t)n, sw_config{});
+    p->base.assign((size_t)n, 0);
+    size_t off = 0;
+    p->ntiles = p->ngroups = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        sw_config &c = p->cfg[(size_t)r];
+        sw_config_init(&c, L[r], beta[r], J[r], seed[r]);
+        c.init = init;
+        c.tile = (int32_t)p->tw;
+        c.ring = ring > 0 ? ring : kDefaultBatchRing;
+        const int rc = validate(&c);
+        if (rc != SW_OK) return fail(rc, "replica " + std::to_string(r) + ": " + g_err);
+        const Layout lo = layout_of(c);
+        p->base[(size_t)r] = off;
+        off = align_up(off + lo.total);
+        const uint32_t nt = (uint32_t)((c.L / p->tw) * (c.L / p->tw));
+        p->ntiles += nt;
+        p->ngroups += (nt + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
+    }
+    p->nwmap = (p->ntiles + 3u) & ~3u;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    p->devs = take((size_t)n * sizeof(Dev));
+    p->tmap = take((size_t)p->ntiles * 4);
+    p->wmap = take((size_t)p->nwmap * 4);
+    p->gmap = take((size_t)p->ngroups * 4);
+    p->total = off;
+    return SW_OK;
+}
+
+int batch_device(const sw_batch *b) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != b->device) HIP_TRY(hipSetDevice(b->device));
+    return SW_OK;
+}
+
+void batch_drop_graph(sw_batch *b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->graph_tried = false;
+}
+
+// One batched sweep captured as a graph (five kernel nodes); on any capture
+// failure the kernels are launched directly.
+void batch_ensure_graph(sw_batch *b) {
+    if (b->graph_tried) return;
+    b->graph_tried = true;
+    if (b->stream == nullptr) return;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    const hipError_t le = swmi::launch_batch_sweep(b->bd, b->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+    if (le != hipSuccess || ce != hipSuccess || g == nullptr) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return;
+    }
+    hipGraphExec_t ge = nullptr;
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return;
+    }
+    b->graph = g;
+    b->gexec = ge;
+}
+
+int batch_check_replica(const sw_batch *b, int32_t r) {
+    if (!b) return fail(SW_EINVAL, "batch is NULL");
+    if (r < 0 || (size_t)r >= b->dev.size()) return fail(SW_ERANGE, "replica index out of range");
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sw_batch_workspace_bytes(int32_t n, const int32_t *L, int64_t ring) {
+    if (n < 1 || n > swmi::kMaxReplicas || !L) return 0;
+    std::vector<double> beta((size_t)n, 0.0), J((size_t)n, 1.0);
+    std::vector<uint64_t> seed((size_t)n, 0u);
+    BatchPlan p;
+    if (plan_batch(n, L, beta.data(), J.data(), seed.data(), SW_INIT_HOT, ring, &p) != SW_OK) return 0;
+    return p.total;
+}
+
+int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
+                    int32_t init, int64_t ring, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                    sw_batch **out) {
+    if (!out) return fail(SW_EINVAL, "out is NULL");
+    *out = nullptr;
+    BatchPlan p;
+    int rc = plan_batch(n, L, beta, J, seed, init, ring, &p);
+    if (rc != SW_OK) return rc;
+    if (dev_workspace && ws_bytes < p.total)
+        return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes");
+    if (dev_workspace && ((uintptr_t)dev_workspace % kAlign) != 0)
+        return fail(SW_EINVAL, "workspace must be 256-byte aligned");
+    sw_batch *b = new (std::nothrow) sw_batch();
+    if (!b) return fail(SW_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "hipGetDevice");
+    }
+    if (dev_workspace) {
+        b->ws = dev_workspace;
+        b->ws_bytes = ws_bytes;
+        b->own_ws = false;
+        b->stream = (hipStream_t)hip_stream;
+        b->own_stream = false;
+    } else {
+        e = hipMalloc(&b->ws, p.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete b;
+            return fail(SW_ENOMEM, "hipMalloc of " + std::to_string(p.total) + " bytes failed");
+        }
+        b->ws_bytes = p.total;
+        b->own_ws = true;
+        if (hip_stream) {
+            b->stream = (hipStream_t)hip_stream;
+            b->own_stream = false;
+        } else {
+            e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                (void)hipFree(b->ws);
+                delete b;
+                return hip_fail(e, "hipStreamCreateWithFlags");
+            }
+            b->own_stream = true;
+        }
+    }
+    char *base = (char *)b->ws;
+    b->cfg = p.cfg;
+    b->dev.resize(p.cfg.size());
+    std::vector<uint32_t> tmap, wmap, gmap;
+    tmap.reserve(p.ntiles);
+    gmap.reserve(p.ngroups);
+    for (size_t r = 0; r < p.cfg.size(); ++r) {
+        b->dev[r] = make_dev(p.cfg[r], base + p.base[r], layout_of(p.cfg[r]));
+        const uint32_t tag = (uint32_t)r << swmi::kMapShift;
+        for (uint32_t t = 0; t < b->dev[r].ntiles; ++t) tmap.push_back(tag | t);
+        for (uint32_t g = 0; g < b->dev[r].ngroups; ++g) gmap.push_back(tag | g);
+    }
+    wmap = tmap;
+    wmap.resize(p.nwmap, swmi::kMapNone);
+    b->bd.devs = (const Dev *)(base + p.devs);
+    b->bd.tmap = (const uint32_t *)(base + p.tmap);
+    b->bd.wmap = (const uint32_t *)(base + p.wmap);
+    b->bd.gmap = (const uint32_t *)(base + p.gmap);
+    b->bd.n = (uint32_t)p.cfg.size();
+    b->bd.ntiles = p.ntiles;
+    b->bd.nwmap = p.nwmap;
+    b->bd.ngroups = p.ngroups;
+    b->bd.tw = p.tw;
+
+    e = hipMemsetAsync(b->ws, 0, p.total, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + p.devs, b->dev.data(), b->dev.size() * sizeof(Dev), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + p.tmap, tmap.data(), tmap.size() * 4, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + p.wmap, wmap.data(), wmap.size() * 4, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + p.gmap, gmap.data(), gmap.size() * 4, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "setting up the batch workspace");
+        sw_batch_destroy(b);
+        return rc;
+    }
+    rc = sw_batch_reset(b, init);
+    if (rc != SW_OK) {
+        const std::string msg = g_err;
+        sw_batch_destroy(b);
+        return fail(rc, msg);
+    }
+    *out = b;
+    return SW_OK;
+}
+
+int sw_batch_reset(sw_batch *b, int32_t init_mode) {
+    if (!b) return fail(SW_EINVAL, "batch is NULL");
+    if (init_mode != SW_INIT_HOT && init_mode != SW_INIT_COLD)
+        return fail(SW_EINVAL, "init_mode must be SW_INIT_HOT or SW_INIT_COLD");
+    int rc = batch_device(b);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const uint64_t zero = 0;
+    for (const Dev &d : b->dev) {
+        HIP_TRY(hipMemcpyAsync(d.tdev, &zero, sizeof(zero), hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(swmi::launch_init(d, init_mode == SW_INIT_COLD ? 1 : 0, b->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->next_sweep = 0;
+    b->first_valid = 0;
+    return SW_OK;
+}
+
+int sw_batch_sweep(sw_batch *b, int64_t n) {
+    if (!b) return fail(SW_EINVAL, "batch is NULL");
+    if (n < 0) return fail(SW_EINVAL, "n must be >= 0");
+    if (n == 0) return SW_OK;
+    int rc = batch_device(b);
+    if (rc != SW_OK) return rc;
+    batch_ensure_graph(b);
+    for (int64_t i = 0; i < n; ++i) {
+        if (b->gexec)
+            HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
+        else
+            HIP_TRY(swmi::launch_batch_sweep(b->bd, b->stream));
+    }
+    HIP_TRY(swmi::launch_batch_resolve(b->bd, b->stream));
+    b->next_sweep += (uint64_t)n;
+    return SW_OK;
+}
+
+int sw_batch_sync(sw_batch *b) {
+    if (!b) return fail(SW_EINVAL, "batch is NULL");
+    int rc = batch_device(b);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return SW_OK;
+}
+
+int sw_batch_series(sw_batch *b, int32_t r, int64_t first, int64_t count, sw_obs *out) {
+    int rc = batch_check_replica(b, r);
+    if (rc != SW_OK) return rc;
+    if (count < 0 || (count > 0 && !out)) return fail(SW_EINVAL, "bad count or NULL out");
+    if (count == 0) return SW_OK;
+    if (first < (int64_t)b->first_valid || first + count > (int64_t)b->next_sweep)
+        return fail(SW_ERANGE, "records requested outside the sweeps run since the last reset");
+    const Dev &d = b->dev[(size_t)r];
+    const uint64_t cap = d.ring_cap;
+    if ((uint64_t)(b->next_sweep - (uint64_t)first) > cap) return fail(SW_ERANGE, "records requested have left the ring");
+    rc = batch_device(b);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    int64_t done = 0;
+    while (done < count) {
+        const uint64_t idx = (uint64_t)(first + done) % cap;
+        const int64_t chunk = (int64_t)std::min<uint64_t>((uint64_t)(count - done), cap - idx);
+        HIP_TRY(hipMemcpyAsync(out + done, d.ring + idx, (size_t)chunk * sizeof(sw_obs), hipMemcpyDeviceToHost,
+                               b->stream));
+        done += chunk;
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return SW_OK;
+}
+
+int sw_batch_observables(sw_batch *b, sw_obs *out) {
+    if (!b || !out) return fail(SW_EINVAL, "batch or out is NULL");
+    if (b->next_sweep == b->first_valid) return fail(SW_ESTATE, "no sweep has run since the last reset");
+    int rc = batch_device(b);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const uint64_t t = b->next_sweep - 1u;
+    for (size_t r = 0; r < b->dev.size(); ++r) {
+        const Dev &d = b->dev[r];
+        HIP_TRY(hipMemcpyAsync(out + r, d.ring + t % d.ring_cap, sizeof(sw_obs), hipMemcpyDeviceToHost, b->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return SW_OK;
+}
+
+int sw_batch_get_spins(sw_batch *b, int32_t r, int8_t *host, int64_t n) {
+    int rc = batch_check_replica(b, r);
+    if (rc != SW_OK) return rc;
+    if (!host) return fail(SW_EINVAL, "host is NULL");
+    const Dev &d = b->dev[(size_t)r];
+    if (n != (int64_t)d.L * d.L) return fail(SW_ERANGE, "n must equal L*L of the replica");
+    rc = batch_device(b);
+    if (rc != SW_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(host, d.spins[b->next_sweep & 1u], (size_t)n, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return SW_OK;
+}
+
+int32_t sw_batch_size(const sw_batch *b) { return b ? (int32_t)b->dev.size() : 0; }
+int64_t sw_batch_next_sweep(const sw_batch *b) { return b ? (int64_t)b->next_sweep : -1; }
+int32_t sw_batch_lattice(const sw_batch *b, int32_t r) {
+    return (b && r >= 0 && (size_t)r < b->dev.size()) ? (int32_t)b->dev[(size_t)r].L : 0;
+}
+uint32_t sw_batch_threshold(const sw_batch *b, int32_t r) {
+    return (b && r >= 0 && (size_t)r < b->dev.size()) ? b->dev[(size_t)r].T : 0u;
+}
+int32_t sw_batch_tile(const sw_batch *b) { return b ? (int32_t)b->bd.tw : 0; }
+
+void sw_batch_destroy(sw_batch *b) {
+    if (!b) return;
+    (void)batch_device(b);
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    if (b->own_ws && b->ws) (void)hipFree(b->ws);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
 }
 
 }  // extern "C"

@@ -67,4 +67,25 @@ hipError_t launch_stage(const Dev &d, int stage, hipStream_t s);
 hipError_t launch_sweep(const Dev &d, hipStream_t s);
 hipError_t launch_resolve(const Dev &d, hipStream_t s);
 
+// Batched sweeps: each kernel of a sweep runs once over a table of
+// independent lattices (replicas), each with its own Dev, so a batch costs
+// five launches per sweep whatever its size.  The maps list the work units
+// of every replica: entry = replica << kMapShift | unit.
+constexpr uint32_t kMapShift = 20;
+constexpr uint32_t kMapMask = (1u << kMapShift) - 1u;
+constexpr uint32_t kMapNone = 0xFFFFFFFFu;
+constexpr int32_t kMaxReplicas = 4096;
+
+struct BatchDev {
+    const Dev *devs;       // [n] the replicas' Dev, in device memory
+    const uint32_t *tmap;  // [ntiles] one entry per tile (k_tile, k_resolve)
+    const uint32_t *wmap;  // [nwmap] one per wavefront of k_union, kMapNone-padded to 4
+    const uint32_t *gmap;  // [ngroups] one per group of kGroupTiles tiles (k_flatten, k_roots)
+    uint32_t n, ntiles, nwmap, ngroups, tw;
+};
+
+hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s);
+hipError_t launch_batch_sweep(const BatchDev &b, hipStream_t s);
+hipError_t launch_batch_resolve(const BatchDev &b, hipStream_t s);
+
 }  // namespace swmi

@@ -118,6 +118,35 @@ __device__ __forceinline__ void lds_union2(uint32_t *par, uint32_t a, uint32_t b
         b = expected;
     }
 }
+// Union for the tile kernel, whose parent words carry other data in their
+// high halves (a work list while the unions run): parents are the low 16
+// bits, and the compare-and-swap that links the larger root under the
+// smaller keeps the high half it read.  A failed swap (another lane linked
+// the root, or the high half changed) resumes from what it found.
+__device__ __forceinline__ void lds_union_lo(uint32_t *par, uint32_t a, uint32_t b) {
+    while (true) {
+        uint32_t wa = lds_load(&par[a]), wb = lds_load(&par[b]);
+        uint32_t pa = wa & 0xFFFFu, pb = wb & 0xFFFFu;
+        while (pa != a || pb != b) {
+            a = pa;
+            b = pb;
+            wa = lds_load(&par[a]);
+            wb = lds_load(&par[b]);
+            pa = wa & 0xFFFFu;
+            pb = wb & 0xFFFFu;
+        }
+        if (a == b) return;
+        const bool ahi = a > b;
+        const uint32_t hi = ahi ? a : b, lo = ahi ? b : a;
+        uint32_t expected = ahi ? wa : wb;
+        const uint32_t desired = (expected & 0xFFFF0000u) | lo;
+        if (__hip_atomic_compare_exchange_strong(&par[hi], &expected, desired, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+        a = lo;
+        b = expected & 0xFFFFu;
+    }
+}
 // Root of a once the unions are done (read-only; the high half of a root's
 // word may already hold its cluster size).
 __device__ __forceinline__ uint32_t lds_root(const uint32_t *par, uint32_t a) {
@@ -202,32 +231,34 @@ __device__ __forceinline__ uint32_t byte_at(const uint4 &v, int q) {
     return (w >> (8 * (q & 3))) & 0xFFu;
 }
 
-// Shared front end of k_tile and k_resolve: the table that maps this tile's
-// node codes of the previous sweep to spins.
+// Shared front end of k_tile and k_resolve: the table that maps every byte
+// of this tile's previous output to its spin as an up bit (1 for +1): final
+// spins 0x01 / 0xFF map to themselves, node code 2 + k to the spin of node
+// k's root.
 template <int TW>
-__device__ __forceinline__ void load_table(const Dev &d, uint32_t tile, uint32_t pp, int8_t *s_tab,
+__device__ __forceinline__ void load_table(const Dev &d, uint32_t tile, uint32_t pp, uint8_t *s_tab,
                                            uint32_t tid) {
     constexpr int NT = TW * TW / 16;
     const uint32_t nnodes = d.ntiles * kNodeSlots;
     const uint32_t kprev = min(d.nk[pp][tile], 252u);
     const uint32_t *par_prev = d.parent[pp];
     for (uint32_t b = tid; b < 256u; b += NT) {
-        int8_t val = (b == 0xFFu) ? (int8_t)-1 : (int8_t)1;
+        uint8_t val = b == 0xFFu ? 0u : 1u;
         const uint32_t k = b - 2u;
         if (k < kprev) {
             uint32_t p = par_prev[tile * kNodeSlots + k];
             p = p < nnodes ? p : 0u;
-            val = d.rspin[p];
+            val = d.rspin[p] > 0 ? 1u : 0u;
         }
         s_tab[b] = val;
     }
 }
 
 template <int TW>
-__device__ __forceinline__ uint32_t decode16(const uint4 &v, const int8_t *s_tab) {
+__device__ __forceinline__ uint32_t decode16(const uint4 &v, const uint8_t *s_tab) {
     uint32_t up = 0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) up |= (uint32_t)(s_tab[byte_at(v, q)] > 0) << q;
+    for (int q = 0; q < 16; ++q) up |= (uint32_t)s_tab[byte_at(v, q)] << q;
     return up;
 }
 
@@ -252,7 +283,7 @@ __device__ __forceinline__ uint32_t decode16_remote(const uint4 &v, uint32_t til
 // collects the cluster size and, after numbering, the output byte.
 // =====================================================================
 template <int TW>
-__global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
+__device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     using Row = typename RowOf<TW>::T;
     constexpr int NT = TW * TW / 16;
     constexpr uint32_t RPT = TW / 16;
@@ -260,9 +291,13 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     constexpr int NW = NS / 32;
     constexpr int NWAVE = (NT + 63) / 64;
 
-    // per site: low 16 bits parent; high 16 bits cluster size (roots), then
-    // the root's output byte
-    __shared__ uint32_t s_par[NS];
+    // One word per site, rows padded to PS = TW + 1 words so that the 16
+    // sites a lane gathers at equal offsets fall in distinct banks.  Low 16
+    // bits: parent (a padded index).  High 16 bits: the union work list while
+    // the unions run, then the cluster size (roots), then the root's output
+    // byte.
+    constexpr uint32_t PS = TW + 1;
+    __shared__ uint32_t s_par[TW * PS];
     __shared__ Row s_up[TW + 1];
     __shared__ Row s_ebnb[2 * TW];  // bond masks to E (rows 0..TW-1) and N (rows TW..2TW-1)
     Row *const s_eb = s_ebnb;
@@ -273,7 +308,7 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     __shared__ uint32_t s_xe[(TW + 31) / 32];
     __shared__ uint32_t s_bf[NW];
     __shared__ uint32_t s_pf[NW];
-    __shared__ int8_t s_tab[256];
+    __shared__ uint8_t s_tab[256];
     __shared__ uint32_t s_hist[12];
     // root | size << 16 of each node; for 64-wide tiles it reuses the bond
     // masks, which are dead once the unions are done
@@ -284,7 +319,6 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
 
     const uint32_t tid = threadIdx.x;
     const uint32_t L = d.L, ntx = d.ntx;
-    const uint32_t tile = tile_of_block(blockIdx.x, d.ntiles);
     const uint32_t tx = tile % ntx, ty = tile / ntx;
     const uint64_t tsw = *d.tdev;
     const uint32_t t = (uint32_t)tsw;
@@ -299,7 +333,8 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     const uint32_t gy = ty * TW + ly, gx0 = tx * TW + x0;
     const uint32_t east = ty * ntx + (tx + 1u == ntx ? 0u : tx + 1u);
     const uint32_t north = (ty + 1u == ntx ? 0u : ty + 1u) * ntx + tx;
-    const uint32_t rowbase = ly * TW;
+    const uint32_t rowbase = ly * PS;  // padded index of the row's first site
+    const uint32_t srow = ly * TW;     // site index of the row's first site
 
     // ---- issue the spin loads first, then build the node table
     const uint4 v = *reinterpret_cast<const uint4 *>(sin + (size_t)gy * L + gx0);
@@ -390,56 +425,91 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     const Row B0 = (Row)~(Row)(E0 << 1);
     const uint32_t st = (uint32_t)(B0 >> x0) & 0xFFFFu;
     const uint32_t rs0 = rowbase + hsb_le(B0, x0);
-    {
-        uint32_t rs[16];
-        uint32_t cur = rs0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if ((st >> q) & 1u) cur = rowbase + x0 + (uint32_t)q;
-            rs[q] = cur;
-        }
-        uint4 *dst = reinterpret_cast<uint4 *>(&s_par[rowbase + x0]);
-        dst[0] = make_uint4(rs[0], rs[1], rs[2], rs[3]);
-        dst[1] = make_uint4(rs[4], rs[5], rs[6], rs[7]);
-        dst[2] = make_uint4(rs[8], rs[9], rs[10], rs[11]);
-        dst[3] = make_uint4(rs[12], rs[13], rs[14], rs[15]);
-    }
-    __syncthreads();
-
-    // ---- vertical bonds join runs of adjacent rows (one union per group of
-    // vertical bonds that connect the same pair of runs)
+    uint32_t r = 0u;  // representative vertical bonds of this segment
     if (ly + 1u < (uint32_t)TW) {
         const Row V = s_nb[ly];
         const Row E1 = s_eb[ly + 1];
         const Row R = V & (Row)~(Row)((V << 1) & (E0 << 1) & (E1 << 1));
-        uint32_t r = (uint32_t)(R >> x0) & 0xFFFFu;
-        while (r) {
-            const uint32_t i = (uint32_t)__ffs((int)r) - 1u;
-            r &= r - 1u;
-            lds_union2(s_par, rowbase + x0 + i, rowbase + TW + x0 + i);
+        r = (uint32_t)(R >> x0) & 0xFFFFu;
+    }
+    {
+        uint32_t cur = rs0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if ((st >> q) & 1u) cur = rowbase + x0 + (uint32_t)q;
+            s_par[rowbase + x0 + q] = cur;
         }
+        if (seg == RPT - 1u) s_par[rowbase + TW] = 0u;  // pad word: list slot only
     }
     __syncthreads();
 
-    // ---- every run start to its root; cluster sizes; clusters that touch
-    // the tile edge
+    // ---- vertical bonds join runs of adjacent rows.  One union per group of
+    // vertical bonds that connect the same pair of runs; each wavefront lists
+    // its unions in the high halves of its own rows' words and then works
+    // through the list 64 at a time, so that lanes with many bonds do not
+    // hold up the rest.
+    const uint32_t lane = tid & 63u;
+    const uint32_t wbase = (tid >> 6) * (64u / RPT) * PS;
+    uint32_t nlist;
+    {
+        const uint32_t c = __popc(r);
+        uint32_t pre = 0u;
+        nlist = 0u;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const uint64_t bal = __ballot((c >> j) & 1u);
+            pre += (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))
+                   << j;
+            nlist += (uint32_t)__popcll(bal) << j;
+        }
+        uint32_t w = wbase + pre, rr = r;
+        while (rr) {
+            const uint32_t i = (uint32_t)__ffs((int)rr) - 1u;
+            rr &= rr - 1u;
+            __hip_atomic_fetch_or(&s_par[w], (rowbase + x0 + i) << 16, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+            ++w;
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = lane; k < nlist; k += 64u) {
+        const uint32_t n = lds_load(&s_par[wbase + k]) >> 16;
+        __hip_atomic_fetch_and(&s_par[wbase + k], 0xFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        lds_union_lo(s_par, n, n + PS);
+    }
+    __syncthreads();
+
+    // ---- cluster sizes and edge contact.  A piece is the part of a run
+    // inside this lane's 16 sites; every piece adds its length to the root
+    // of its run, pieces on the tile edge mark the root, and every run start
+    // is pointed at its root.
     uint32_t rootmask = 0u;
     {
-        const bool edge_row = (ly == 0u) || (ly == (uint32_t)TW - 1u);
-        uint32_t m = st;
+        const uint32_t pst = st | 1u;  // piece starts
+        const uint32_t nxt = pst | 0x10000u;
+        uint32_t em = (ly == 0u || ly == (uint32_t)TW - 1u) ? pst : 0u;
+        if (seg == 0u) em |= 1u;
+        if (seg == RPT - 1u) em |= 1u << (31u - (uint32_t)__clz((int)pst));
+        uint32_t m = pst;
         while (m) {
             const uint32_t i = (uint32_t)__ffs((int)m) - 1u;
             m &= m - 1u;
-            const uint32_t n = rowbase + x0 + i;
+            const bool is_rs = (st >> i) & 1u;
+            const uint32_t n = is_rs ? rowbase + x0 + i : rs0;
             const uint32_t root = lds_root(s_par, n);
-            if (root != n)
-                atomicMin(&s_par[n], root);
-            else
-                rootmask |= 1u << i;
-            const uint32_t len = run_len_row<Row>(B0, x0 + i);
-            atomicAdd(&s_par[root], len << 16);
-            if (edge_row || x0 + i == 0u || x0 + i + len == (uint32_t)TW)
-                atomicOr(&s_bf[root >> 5], 1u << (root & 31u));
+            if (is_rs) {
+                if (root != n)
+                    __hip_atomic_store(&s_par[n], root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                else
+                    rootmask |= 1u << i;
+            }
+            const uint32_t len = (uint32_t)__ffs((int)(nxt >> (i + 1u)));
+            __hip_atomic_fetch_add(&s_par[root], len << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if ((em >> i) & 1u) {
+                const uint32_t rsite = root - root / PS;
+                atomicOr(&s_bf[rsite >> 5], 1u << (rsite & 31u));
+            }
         }
     }
     __syncthreads();
@@ -473,42 +543,46 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     __syncthreads();
 
     // ---- roots: output byte into the root's word; node entries staged in
-    // LDS; interior-cluster statistics (bins 0-2 in registers)
-    uint32_t n_int = 0u, max_int = 0u, sq_int = 0u, h0 = 0u, h1 = 0u, h2 = 0u;
-    while (rootmask) {
-        const uint32_t q = (uint32_t)__ffs((int)rootmask) - 1u;
-        rootmask &= rootmask - 1u;
-        const uint32_t root = rowbase + x0 + q;
-        const uint32_t S = s_par[root] >> 16;
-        const uint32_t w = s_bf[root >> 5];
-        const uint32_t bit = 1u << (root & 31u);
-        uint32_t code;
-        if (w & bit) {
-            const uint32_t k = s_pf[root >> 5] + __popc(w & (bit - 1u));
-            s_node[k] = root | (S << 16);
-            code = 2u + k;
-        } else {
-            code = ((uint32_t)(s_fb[ly] >> (x0 + q)) & 1u) ? 0xFFu : 0x01u;
-            ++n_int;
-            max_int = max(max_int, S);
-            sq_int += S * S;
-            if (S == 1u)
-                ++h0;
-            else if (S < 4u)
-                ++h1;
-            else if (S < 8u)
-                ++h2;
-            else
-                atomicAdd(&s_hist[31 - __clz((int)S)], 1u);
-            if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
+    // LDS; interior-cluster statistics (size classes 0-2 packed in one
+    // register, 10 bits each)
+    uint32_t n_int = 0u, max_int = 0u, sq_int = 0u, hpk = 0u;
+    {
+        const uint32_t sbase = srow + x0;  // site index of this lane's first site
+        const uint32_t bfw = s_bf[sbase >> 5];
+        const uint32_t bsh = sbase & 31u;
+        const uint32_t bmask = (bfw >> bsh) & 0xFFFFu;
+        const uint32_t kbase = s_pf[sbase >> 5] + __popc(bfw & ((1u << bsh) - 1u));
+        const uint32_t fl = (uint32_t)(s_fb[ly] >> x0) & 0xFFFFu;
+        while (rootmask) {
+            const uint32_t q = (uint32_t)__ffs((int)rootmask) - 1u;
+            rootmask &= rootmask - 1u;
+            const uint32_t root = rowbase + x0 + q;
+            const uint32_t S = s_par[root] >> 16;
+            uint32_t code;
+            if ((bmask >> q) & 1u) {
+                const uint32_t k = kbase + __popc(bmask & ((1u << q) - 1u));
+                s_node[k] = (sbase + q) | (S << 16);
+                code = 2u + k;
+            } else {
+                code = ((fl >> q) & 1u) ? 0xFFu : 0x01u;
+                ++n_int;
+                max_int = max(max_int, S);
+                sq_int += S * S;
+                const uint32_t bin = 31u - (uint32_t)__clz((int)S);
+                if (bin < 3u)
+                    hpk += 1u << (10u * bin);
+                else
+                    atomicAdd(&s_hist[bin], 1u);
+                if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
+            }
+            s_par[root] = root | (code << 16);
         }
-        s_par[root] = root | (code << 16);
     }
     __syncthreads();
     // node tables of this tile, written in node order
     for (uint32_t k = tid; k < s_k; k += NT) {
-        const uint32_t e = s_node[k], root = e & 0xFFFFu, node = tile * kNodeSlots + k;
-        d.key[node] = (ty * TW + root / TW) * L + tx * TW + root % TW;
+        const uint32_t e = s_node[k], site = e & 0xFFFFu, node = tile * kNodeSlots + k;
+        d.key[node] = (ty * TW + site / TW) * L + tx * TW + site % TW;
         d.nsize[node] = e >> 16;
         par_cur[node] = node;
     }
@@ -533,9 +607,10 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
         for (int q = 0; q < 16; ++q) {
             if ((st >> q) & 1u) cur = rowbase + x0 + (uint32_t)q;
             const uint32_t root = s_par[cur] & 0xFFFFu;
+            const uint32_t rsite = root - root / PS;
             const uint32_t code = (out[q >> 2] >> (8 * (q & 3))) & 0xFFu;
             lab[q] = (code >= 2u && code < 254u) ? (0x80000000u | (tile * kNodeSlots + code - 2u))
-                                                 : (ty * TW + root / TW) * L + tx * TW + root % TW;
+                                                 : (ty * TW + rsite / TW) * L + tx * TW + rsite % TW;
         }
         uint4 *lp = reinterpret_cast<uint4 *>(d.labels + (size_t)gy * L + gx0);
         lp[0] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
@@ -555,6 +630,7 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
             *reinterpret_cast<uint4 *>(eg + 3 * TW + x0) =
                 make_uint4(out[0] - 0x02020202u, out[1] - 0x02020202u, out[2] - 0x02020202u, out[3] - 0x02020202u);
     }
+    uint32_t h0 = hpk & 0x3FFu, h1 = (hpk >> 10) & 0x3FFu, h2 = hpk >> 20;
 
     // ---- workgroup reductions -> tile partial
 #pragma unroll
@@ -609,15 +685,27 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
     }
 }
 
+template <int TW>
+__global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
+    tile_body<TW>(d, tile_of_block(blockIdx.x, d.ntiles));
+}
+
+// Batched launches run the same bodies over a table of replicas (map
+// entries replica << kMapShift | unit index), so every replica's bits are
+// those of its own plain sweep.
+template <int TW>
+__global__ __launch_bounds__(TW *TW / 16) void k_tile_b(const Dev *devs, const uint32_t *map) {
+    const uint32_t e = map[blockIdx.x];
+    tile_body<TW>(devs[e >> kMapShift], e & kMapMask);
+}
+
 // =====================================================================
 // k_union: bonds that leave a tile through its E or N edge join the nodes
 // on both sides (Sec. 2.3, global part).  One wavefront per tile.
 // =====================================================================
 template <int TW>
-__global__ __launch_bounds__(256) void k_union(Dev d) {
-    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint32_t tile = blockIdx.x * 4u + wv;
-    if (tile >= d.ntiles) return;
+__device__ __forceinline__ void union_body(const Dev &d, const uint32_t tile) {
+    const uint32_t lane = threadIdx.x & 63u;
     const uint32_t pc = (uint32_t)(*d.tdev & 1u);
     uint32_t *par = d.parent[pc];
     const uint32_t ntx = d.ntx, tx = tile % ntx, ty = tile / ntx;
@@ -646,6 +734,18 @@ __global__ __launch_bounds__(256) void k_union(Dev d) {
         const uint32_t b = isn ? north * kNodeSlots + egn[2 * TW + i] : east * kNodeSlots + ege[0 * TW + i];
         one_pass(isn ? xn : xe, i, a, b);
     }
+}
+
+template <int TW>
+__global__ __launch_bounds__(256) void k_union(Dev d) {
+    const uint32_t tile = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (tile < d.ntiles) union_body<TW>(d, tile);
+}
+
+template <int TW>
+__global__ __launch_bounds__(256) void k_union_b(const Dev *devs, const uint32_t *map) {
+    const uint32_t e = map[blockIdx.x * 4u + (threadIdx.x >> 6)];
+    if (e != kMapNone) union_body<TW>(devs[e >> kMapShift], e & kMapMask);
 }
 
 // =====================================================================
@@ -677,7 +777,7 @@ __device__ __forceinline__ void hash_add(uint32_t *hk, uint32_t *hv, uint32_t ke
     atomicAdd(&global_fallback[key], val);
 }
 
-__global__ __launch_bounds__(256) void k_flatten(Dev d) {
+__device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group) {
     __shared__ uint32_t hk[kHashSlots];
     __shared__ uint32_t hv[kHashSlots];
     for (uint32_t i = threadIdx.x; i < (uint32_t)kHashSlots; i += 256u) {
@@ -688,7 +788,7 @@ __global__ __launch_bounds__(256) void k_flatten(Dev d) {
     const uint32_t pc = (uint32_t)(*d.tdev & 1u);
     uint32_t *par = d.parent[pc];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint32_t g0 = blockIdx.x * (uint32_t)kGroupTiles;
+    const uint32_t g0 = group * (uint32_t)kGroupTiles;
     for (uint32_t tt = wv; tt < (uint32_t)kGroupTiles; tt += 4u) {
         const uint32_t tile = g0 + tt;
         if (tile >= d.ntiles) break;
@@ -707,6 +807,13 @@ __global__ __launch_bounds__(256) void k_flatten(Dev d) {
         const uint32_t k = hk[i];
         if (k != kEmpty) atomicAdd(&d.nsize[k], hv[i]);
     }
+}
+
+__global__ __launch_bounds__(256) void k_flatten(Dev d) { flatten_body(d, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_flatten_b(const Dev *devs, const uint32_t *map) {
+    const uint32_t e = map[blockIdx.x];
+    flatten_body(devs[e >> kMapShift], e & kMapMask);
 }
 
 // Canonical labels of sites of cross-tile clusters (only with SW_FLAG_LABELS).
@@ -731,7 +838,7 @@ __global__ __launch_bounds__(256) void k_relabel(Dev d) {
 // k_roots: new spin of every cross-tile cluster (Sec. 2.4) and the cluster
 // statistics of the workgroup's tiles -> group partial.
 // =====================================================================
-__global__ __launch_bounds__(256) void k_roots(Dev d) {
+__device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
     __shared__ uint32_t s_hist[33];
     __shared__ uint64_t s_red[4][5];
     if (threadIdx.x < 33u) s_hist[threadIdx.x] = 0u;
@@ -740,7 +847,7 @@ __global__ __launch_bounds__(256) void k_roots(Dev d) {
     const uint32_t t = (uint32_t)tsw, pc = (uint32_t)(tsw & 1u);
     const uint32_t *par = d.parent[pc];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint32_t g0 = blockIdx.x * (uint32_t)kGroupTiles;
+    const uint32_t g0 = group * (uint32_t)kGroupTiles;
     uint64_t n = 0, mx = 0, sq = 0;
     int64_t e = 0, m = 0;
     for (uint32_t tt = wv; tt < (uint32_t)kGroupTiles; tt += 4u) {
@@ -789,7 +896,7 @@ __global__ __launch_bounds__(256) void k_roots(Dev d) {
         s_red[wv][4] = (uint64_t)m;
     }
     __syncthreads();
-    uint64_t *gp = d.gpart + (size_t)blockIdx.x * kGroupPart;
+    uint64_t *gp = d.gpart + (size_t)group * kGroupPart;
     if (threadIdx.x == 0u) {
         uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
         for (int w = 0; w < 4; ++w) {
@@ -808,11 +915,67 @@ __global__ __launch_bounds__(256) void k_roots(Dev d) {
     if (threadIdx.x < 33u) gp[GP_HIST + threadIdx.x] = s_hist[threadIdx.x];
 }
 
+__global__ __launch_bounds__(256) void k_roots(Dev d) { roots_body(d, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_roots_b(const Dev *devs, const uint32_t *map) {
+    const uint32_t e = map[blockIdx.x];
+    roots_body(devs[e >> kMapShift], e & kMapMask);
+}
+
 // =====================================================================
 // k_record: fold group partials (mode 0, end of a sweep) or tile partials
 // (mode 1, end of k_resolve) into the record ring; the last workgroup to
 // finish writes the record and clears the accumulator.
 // =====================================================================
+// One partial into the workgroup's LDS accumulator.
+__device__ __forceinline__ void record_add(const Dev &d, uint32_t item, int mode, uint64_t *s_acc) {
+    unsigned long long *a = reinterpret_cast<unsigned long long *>(s_acc);
+    if (mode == 0) {
+        const uint64_t *gp = d.gpart + (size_t)item * kGroupPart;
+        atomicAdd(&a[GP_N], (unsigned long long)gp[GP_N]);
+        atomicMax(&a[GP_MAX], (unsigned long long)gp[GP_MAX]);
+        atomicAdd(&a[GP_SQ], (unsigned long long)gp[GP_SQ]);
+        atomicAdd(&a[GP_E], (unsigned long long)gp[GP_E]);
+        atomicAdd(&a[GP_M], (unsigned long long)gp[GP_M]);
+        for (int b = 0; b < 33; ++b)
+            if (gp[GP_HIST + b]) atomicAdd(&a[GP_HIST + b], (unsigned long long)gp[GP_HIST + b]);
+    } else {
+        const int32_t *tp = d.tpart + (size_t)item * kTilePart;
+        atomicAdd(&a[GP_E], (unsigned long long)(int64_t)tp[TP_E]);
+        atomicAdd(&a[GP_M], (unsigned long long)(int64_t)tp[TP_M]);
+    }
+}
+
+// Writes the totals in s_acc: mode 0 the record of sweep t = *tdev (cluster
+// statistics) and t advances; both modes the energy and magnetisation of
+// the configuration sweep t-1 left, into record t-1.
+__device__ __forceinline__ void record_write(const Dev &d, const uint64_t *s_acc, int mode) {
+    const uint32_t tid = threadIdx.x;
+    const uint64_t tsw = *d.tdev;
+    if (mode == 0) {
+        sw_obs *rec = &d.ring[tsw % d.ring_cap];
+        if (tid == 0u) {
+            rec->sweep = tsw;
+            rec->n_clusters = s_acc[GP_N];
+            rec->max_cluster = s_acc[GP_MAX];
+            rec->sum_sq_sizes = s_acc[GP_SQ];
+        }
+        if (tid < 33u) rec->hist_log2[tid] = s_acc[GP_HIST + tid];
+    }
+    if (tid == 0u && tsw >= 1u) {
+        sw_obs *prev = &d.ring[(tsw - 1u) % d.ring_cap];
+        const int64_t e = (int64_t)s_acc[GP_E];
+        prev->e_sum = e;
+        prev->energy = -d.J * (double)e;
+        prev->m_sum = (int64_t)s_acc[GP_M];
+    }
+    __syncthreads();  // every thread has read the sweep index
+    if (tid == 0u) {
+        if (mode == 0) *d.tdev = tsw + 1u;
+        __threadfence();
+    }
+}
+
 __global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode) {
     __shared__ uint64_t s_acc[GP_END];
     __shared__ int s_last;
@@ -820,24 +983,7 @@ __global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode
     if (tid < (uint32_t)GP_END) s_acc[tid] = 0u;
     __syncthreads();
     const uint32_t item = blockIdx.x * 256u + tid;
-    if (item < nitems) {
-        if (mode == 0) {
-            const uint64_t *gp = d.gpart + (size_t)item * kGroupPart;
-            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_N]), (unsigned long long)gp[GP_N]);
-            atomicMax(reinterpret_cast<unsigned long long *>(&s_acc[GP_MAX]), (unsigned long long)gp[GP_MAX]);
-            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_SQ]), (unsigned long long)gp[GP_SQ]);
-            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_E]), (unsigned long long)gp[GP_E]);
-            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_M]), (unsigned long long)gp[GP_M]);
-            for (int b = 0; b < 33; ++b)
-                if (gp[GP_HIST + b])
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_HIST + b]),
-                              (unsigned long long)gp[GP_HIST + b]);
-        } else {
-            const int32_t *tp = d.tpart + (size_t)item * kTilePart;
-            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_E]), (unsigned long long)(int64_t)tp[TP_E]);
-            atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[GP_M]), (unsigned long long)(int64_t)tp[TP_M]);
-        }
-    }
+    if (item < nitems) record_add(d, item, mode, s_acc);
     __syncthreads();
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(d.acc);
     if (tid < (uint32_t)GP_END && s_acc[tid] != 0u) {
@@ -855,33 +1001,30 @@ __global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    if (tid == 0u) {
-        uint64_t v[GP_END];
-        for (int i = 0; i < GP_END; ++i) {
-            v[i] = __hip_atomic_load(&acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&acc[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __hip_atomic_store(&acc[ACC_COUNT], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t tsw = *d.tdev;
-        if (mode == 0) {
-            sw_obs *rec = &d.ring[tsw % d.ring_cap];
-            rec->sweep = tsw;
-            rec->n_clusters = v[GP_N];
-            rec->max_cluster = v[GP_MAX];
-            rec->sum_sq_sizes = v[GP_SQ];
-            for (int b = 0; b < 33; ++b) rec->hist_log2[b] = v[GP_HIST + b];
-        }
-        if (tsw >= 1u) {
-            // observables of the configuration that sweep tsw-1 left
-            sw_obs *prev = &d.ring[(tsw - 1u) % d.ring_cap];
-            const int64_t e = (int64_t)v[GP_E];
-            prev->e_sum = e;
-            prev->energy = -d.J * (double)e;
-            prev->m_sum = (int64_t)v[GP_M];
-        }
-        if (mode == 0) *d.tdev = tsw + 1u;
-        __threadfence();
+    // the last workgroup: take the totals (one field per thread) and clear
+    // the accumulator for the next fold
+    if (tid < (uint32_t)GP_END) {
+        s_acc[tid] = __hip_atomic_load(&acc[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&acc[tid], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (tid == (uint32_t)GP_END)
+        __hip_atomic_store(&acc[ACC_COUNT], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    record_write(d, s_acc, mode);
+}
+
+// Batched record: one workgroup per replica folds all of that replica's
+// partials itself, so no cross-workgroup accumulator is needed.
+__global__ __launch_bounds__(256) void k_record_b(const Dev *devs, int mode) {
+    __shared__ uint64_t s_acc[GP_END];
+    const Dev &d = devs[blockIdx.x];
+    const uint32_t tid = threadIdx.x;
+    if (tid < (uint32_t)GP_END) s_acc[tid] = 0u;
+    __syncthreads();
+    const uint32_t nitems = mode == 0 ? d.ngroups : d.ntiles;
+    for (uint32_t item = tid; item < nitems; item += 256u) record_add(d, item, mode, s_acc);
+    __syncthreads();
+    record_write(d, s_acc, mode);
 }
 
 // =====================================================================
@@ -889,19 +1032,18 @@ __global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode
 // configuration (runs once at the end of every sw_sweep call).
 // =====================================================================
 template <int TW>
-__global__ __launch_bounds__(TW *TW / 16) void k_resolve(Dev d) {
+__device__ __forceinline__ void resolve_body(const Dev &d, const uint32_t tile) {
     constexpr int NT = TW * TW / 16;
     constexpr uint32_t RPT = TW / 16;
     constexpr int NWAVE = (NT + 63) / 64;
     using Row = typename RowOf<TW>::T;
-    __shared__ int8_t s_tab[256];
+    __shared__ uint8_t s_tab[256];
     __shared__ Row s_up[TW + 1];
     __shared__ uint32_t s_eup[(TW + 31) / 32];
     __shared__ int32_t s_red[NWAVE][2];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t L = d.L, ntx = d.ntx;
-    const uint32_t tile = tile_of_block(blockIdx.x, d.ntiles);
     const uint32_t tx = tile % ntx, ty = tile / ntx;
     const uint64_t tsw = *d.tdev;
     const uint32_t pc = (uint32_t)(tsw & 1u), pp = pc ^ 1u;
@@ -967,6 +1109,17 @@ __global__ __launch_bounds__(TW *TW / 16) void k_resolve(Dev d) {
         d.tpart[(size_t)tile * kTilePart + TP_E] = e;
         d.tpart[(size_t)tile * kTilePart + TP_M] = m;
     }
+}
+
+template <int TW>
+__global__ __launch_bounds__(TW *TW / 16) void k_resolve(Dev d) {
+    resolve_body<TW>(d, tile_of_block(blockIdx.x, d.ntiles));
+}
+
+template <int TW>
+__global__ __launch_bounds__(TW *TW / 16) void k_resolve_b(const Dev *devs, const uint32_t *map) {
+    const uint32_t e = map[blockIdx.x];
+    resolve_body<TW>(devs[e >> kMapShift], e & kMapMask);
 }
 
 // Initial spins (Fig. 1): hot = bit 0 of word 0 of Philox({s, 0, 2, 0}),
@@ -1054,6 +1207,52 @@ hipError_t launch_resolve(const Dev &d, hipStream_t s) {
     else
         k_resolve<32><<<d.ntiles, 64, 0, s>>>(d);
     k_record<<<(d.ntiles + 255) / 256, 256, 0, s>>>(d, d.ntiles, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
+    switch (stage) {
+    case 0:
+        if (b.tw == 64)
+            k_tile_b<64><<<b.ntiles, 256, 0, s>>>(b.devs, b.tmap);
+        else
+            k_tile_b<32><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);
+        break;
+    case 1:
+        if (b.tw == 64)
+            k_union_b<64><<<b.nwmap / 4, 256, 0, s>>>(b.devs, b.wmap);
+        else
+            k_union_b<32><<<b.nwmap / 4, 256, 0, s>>>(b.devs, b.wmap);
+        break;
+    case 2:
+        k_flatten_b<<<b.ngroups, 256, 0, s>>>(b.devs, b.gmap);
+        break;
+    case 3:
+        k_roots_b<<<b.ngroups, 256, 0, s>>>(b.devs, b.gmap);
+        break;
+    case 4:
+        k_record_b<<<b.n, 256, 0, s>>>(b.devs, 0);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(const BatchDev &b, hipStream_t s) {
+    for (int stage = 0; stage < kStages; ++stage) {
+        const hipError_t e = launch_batch_stage(b, stage, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_batch_resolve(const BatchDev &b, hipStream_t s) {
+    if (b.tw == 64)
+        k_resolve_b<64><<<b.ntiles, 256, 0, s>>>(b.devs, b.tmap);
+    else
+        k_resolve_b<32><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);
+    k_record_b<<<b.n, 256, 0, s>>>(b.devs, 1);
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_2302_14720_amd as sw
@@ -71,3 +72,26 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu(lib):
     assert lib.sw_sweep(None, 1) == sw.SW_EINVAL
     assert lib.sw_observables(None, None) == sw.SW_EINVAL
     lib.sw_destroy(None)  # no-op
+
+
+def test_batch_workspace_sizes_and_validation():
+    lib = sw.lib()
+    L = np.array([64, 128, 256], dtype=np.int32)
+    n1 = sw.sw_batch_workspace_bytes(L)
+    assert n1 > sum(sw.sw_workspace_bytes(int(x)) // 4 for x in L)
+    assert sw.sw_batch_workspace_bytes(L, ring=4096) > n1
+    assert sw.sw_batch_workspace_bytes(np.array([64, 100], dtype=np.int32)) == 0
+    assert sw.sw_batch_workspace_bytes(np.zeros(0, dtype=np.int32)) == 0
+    assert sw.sw_batch_workspace_bytes(np.full(4097, 64, dtype=np.int32)) == 0
+    # creation is refused before any device call for invalid replicas
+    h = ctypes.c_void_p()
+    b = np.array([0.4, 0.4]), np.array([1.0, 1.0])
+    s = np.array([1, 2], dtype=np.uint64)
+    bad_L = np.array([64, 33], dtype=np.int32)
+    rc = lib.sw_batch_create(2, bad_L.ctypes.data_as(ctypes.c_void_p), b[0].ctypes.data_as(ctypes.c_void_p),
+                             b[1].ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p), 0, 0,
+                             None, 0, None, ctypes.byref(h))
+    assert rc == sw.SW_EINVAL and b"replica 1" in lib.sw_last_error()
+    rc = lib.sw_batch_create(0, None, None, None, None, 0, 0, None, 0, None, ctypes.byref(h))
+    assert rc == sw.SW_EINVAL
+    assert lib.sw_batch_size(None) == 0 and lib.sw_batch_next_sweep(None) == -1

@@ -1,0 +1,129 @@
+"""Batched replicas through the C ABI: every replica's records and spins
+must be bit for bit those of a plain sim with the same parameters (which the
+parity tests tie to the oracle), and small replicas are also compared with
+the oracle directly."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2302_14720_amd as sw
+from paper_2302_14720_amd.replicas import grid_table
+
+pytestmark = pytest.mark.gpu
+
+BETA_C = math.log(1.0 + math.sqrt(2.0)) / 2.0
+FIELDS = ("sweep", "e_sum", "energy", "m_sum", "n_clusters", "max_cluster", "sum_sq_sizes")
+
+
+def _same_records(a, b, where):
+    assert len(a) == len(b), where
+    for f in FIELDS:
+        bad = np.nonzero(a[f] != b[f])[0]
+        assert bad.size == 0, f"{where} field {f}: first mismatch at record {bad[0]}"
+    assert np.array_equal(a["hist_log2"], b["hist_log2"]), f"{where} hist_log2"
+
+
+def _batch(L, beta, seed, **kw):
+    print(f"\n[case] batch n={len(L)} L={list(L)[:8]} {kw}", flush=True)
+    return sw.Batch(L, beta, 1.0, seed, **kw)
+
+
+def _plain(L, beta, seed, n, chunks=None, tile=0, cold=False):
+    with sw.Sim(int(L), float(beta), 1.0, int(seed), tile=tile,
+                init=sw.SW_INIT_COLD if cold else sw.SW_INIT_HOT) as s:
+        for c in (chunks or [n]):
+            s.sweep(c)
+        return s.series(0, n), s.spins()
+
+
+def test_mixed_batch_matches_plain_and_oracle():
+    L = [64, 128, 192, 256, 64, 320, 128]
+    beta = [BETA_C, 0.30, 0.60, BETA_C, 0.0, 0.45, 5.0]
+    seed = [11, 12, 13, 14, 15, 16, 17]
+    n = 25
+    with _batch(L, beta, seed) as b:
+        assert b.tile == 64
+        b.sweep(3)
+        b.sweep(n - 3)
+        last = b.observables()
+        for r in range(len(L)):
+            assert b.threshold(r) == oracle.threshold(beta[r], 1.0)
+            got = b.series(r, 0, n)
+            ref, sp = _plain(L[r], beta[r], seed[r], n)
+            _same_records(got, ref, f"replica {r}")
+            assert np.array_equal(b.spins(r), sp), f"replica {r} spins"
+            assert last[r].tobytes() == got[-1].tobytes()
+            if L[r] <= 128:
+                osp = oracle.init(L[r], seed[r])
+                orec = oracle.run(L[r], 1.0, oracle.threshold(beta[r], 1.0), seed[r], 0, n, osp)
+                _same_records(got, orec, f"replica {r} vs oracle")
+                assert np.array_equal(b.spins(r), osp)
+
+
+def test_tile32_batch_and_cold_start():
+    L = [32, 96, 64, 160]
+    beta = [0.35, BETA_C, 0.5, BETA_C]
+    seed = [21, 22, 23, 24]
+    n = 20
+    with _batch(L, beta, seed, init=sw.SW_INIT_COLD) as b:
+        assert b.tile == 32
+        b.sweep(n)
+        for r in range(len(L)):
+            ref, sp = _plain(L[r], beta[r], seed[r], n, tile=32, cold=True)
+            _same_records(b.series(r, 0, n), ref, f"replica {r}")
+            assert np.array_equal(b.spins(r), sp)
+
+
+def test_reset_replays_the_same_chain():
+    L, beta, seed = [64, 128, 256], [0.41, 0.44, 0.47], [5, 6, 7]
+    with _batch(L, beta, seed) as b:
+        b.sweep(7)
+        first = [b.series(r, 0, 7) for r in range(3)]
+        b.reset()
+        assert b.next_sweep == 0
+        b.sweep(2)
+        b.sweep(5)
+        for r in range(3):
+            _same_records(b.series(r, 0, 7), first[r], f"replica {r} after reset")
+
+
+def test_grid_workload_sampled_replicas():
+    """The 256-replica temperature grid at its full sizes: a few sweeps of the
+    whole batch; sampled replicas against plain sims, every replica against
+    the record invariants."""
+    L, beta, seed = grid_table()
+    n = 4
+    with _batch(L, beta, seed) as b:
+        b.sweep(n)
+        recs = b.observables()
+        for r in (0, 1, 2, 3, 4, 9, 130, 254, 255):
+            ref, sp = _plain(L[r], beta[r], seed[r], n)
+            _same_records(b.series(r, 0, n), ref, f"replica {r}")
+            assert np.array_equal(b.spins(r), sp)
+    N = L.astype(np.int64) ** 2
+    assert np.all(recs["sweep"] == n - 1)
+    assert np.all((recs["e_sum"] - 2 * N) % 4 == 0)
+    assert np.all((recs["m_sum"] - N) % 2 == 0)
+    assert np.all(recs["hist_log2"].sum(axis=1) == recs["n_clusters"])
+    assert np.all(recs["max_cluster"] <= N) and np.all(recs["n_clusters"] >= 1)
+
+
+def test_batch_errors():
+    with pytest.raises(sw.SwError) as e:
+        sw.Batch([64, 100], 0.4, 1.0, 1)
+    assert e.value.code == sw.SW_EINVAL and "replica 1" in str(e.value)
+    with pytest.raises(sw.SwError):
+        sw.Batch([64], -1.0, 1.0, 1)
+    with _batch([64, 64], [0.4, 0.4], [1, 2]) as b:
+        with pytest.raises(sw.SwError) as e:
+            b.observables()
+        assert e.value.code == sw.SW_ESTATE
+        b.sweep(1)
+        with pytest.raises(sw.SwError) as e:
+            b.series(2, 0, 1)
+        assert e.value.code == sw.SW_ERANGE
+        with pytest.raises(sw.SwError) as e:
+            b.series(0, 0, 2)
+        assert e.value.code == sw.SW_ERANGE

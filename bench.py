@@ -135,6 +135,51 @@ def batched_vs_plain(args):
     }
 
 
+def serving(args):
+    """Continuous batching: jobs arrive as a Poisson process (L log-uniform in
+    [128, 4096] rounded to 32, beta uniform in [0.35, 0.55], sweeps uniform in
+    [100, 10^4], seeded), wait for room in a 16 GiB device pool, and are swept
+    together; latency = finish - arrival on the host clock."""
+    import numpy as np
+
+    import paper_2302_14720_amd as sw
+
+    rng = np.random.default_rng(2024)
+    n = args.serve_jobs
+    gaps = rng.exponential(1.0 / args.serve_rate, n)
+    arrive = np.cumsum(gaps) - gaps[0]
+    L = (np.round(np.exp(rng.uniform(np.log(128), np.log(4096), n)) / 32).astype(int) * 32).clip(128, 4096)
+    beta = rng.uniform(0.35, 0.55, n)
+    sweeps = rng.integers(100, 10001, n)
+    work = int((L.astype(np.int64) ** 2 * sweeps).sum())
+    print(f"[bench] serving: {n} jobs, {work:.3e} site-updates", file=sys.stderr, flush=True)
+    srv = sw.Server(16 << 30, max_jobs=256)
+    t0 = time.perf_counter()
+    nxt, finish, ids = 0, {}, {}
+    while len(finish) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arrive[nxt] <= now:
+            ids[srv.submit(int(L[nxt]), float(beta[nxt]), 1.0, 5000 + nxt, int(sweeps[nxt]))] = nxt
+            nxt += 1
+        st = srv.status()
+        if st["active"] == 0 and st["queued"] == 0:
+            time.sleep(max(0.0, min(0.01, arrive[nxt] - now)))
+            continue
+        for jid in srv.step(20):
+            finish[ids[jid]] = time.perf_counter() - t0
+            srv.release(jid)
+    span = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([finish[i] - arrive[i] for i in range(n)])
+    return {
+        "workload": f"{n} jobs, Poisson arrivals at {args.serve_rate} jobs/s, L log-uniform in [128, 4096] "
+                    "(multiples of 32), beta U[0.35, 0.55], sweeps U[100, 10000], hot start, 16 GiB pool",
+        "jobs": n, "site_updates": work, "makespan_s": span,
+        "value": work / span, "unit": "site-updates/s",
+        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +197,8 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=10,
                     help="timed sweeps of the same replicas as plain sims, one sw_sweep per replica per sweep")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--serve-jobs", type=int, default=48, help="jobs of the serving leg (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the serving leg, jobs/s")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for "
                          "HBM byte counters)")
@@ -271,6 +318,7 @@ def main() -> int:
                        "ms_per_step": cdt * 1e3 / args.cold_sweeps,
                        "first_sweep_max_cluster": int(crec["max_cluster"])},
         "batched": None if args.no_batched else batched_vs_plain(args),
+        "serving": serving(args) if args.serve_jobs > 0 else None,
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on one L=%d sweep" % L, file=sys.stderr, flush=True)

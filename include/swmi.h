@@ -244,6 +244,74 @@ int32_t sw_batch_tile(const sw_batch *batch);
 /* Destroys the batch (waits for its stream first); NULL is a no-op. */
 void sw_batch_destroy(sw_batch *batch);
 
+/* ------------------------------------------------------------- serving
+ * A server runs independent jobs -- (L, beta, J, seed, start, number of
+ * sweeps) -- on one GPU.  Jobs wait in a FIFO queue until their buffers fit
+ * in the server's device memory pool and a slot is free; every step then
+ * advances all active jobs together with the batched kernels (continuous
+ * batching: a job leaves as soon as it has run its sweeps, and queued jobs
+ * take its memory).  A job's spins and records are bit for bit those of a
+ * plain sim with the same parameters run alone, whatever else shares the
+ * GPU.  A finished job's records (all of its sweeps) and final spins stay on
+ * the device until sw_server_release. */
+typedef struct sw_server sw_server;
+
+#define SW_JOB_QUEUED 0  /* waiting for memory or a slot                     */
+#define SW_JOB_ACTIVE 1  /* sweeping                                         */
+#define SW_JOB_DONE 2    /* all sweeps run; results readable until released */
+
+typedef struct {
+    int64_t id;
+    int32_t state;         /* SW_JOB_*                                         */
+    int32_t L;
+    int64_t sweeps_done;
+    int64_t sweeps_total;
+    uint64_t bytes;        /* device bytes the job holds while admitted       */
+} sw_job_info;
+
+/* Device bytes a job of side L running `sweeps` sweeps needs (0 if invalid). */
+size_t sw_server_job_bytes(int32_t L, int64_t sweeps);
+
+/* Creates a server with a device memory pool of pool_bytes: `pool` is a
+ * 256-byte-aligned device buffer the caller keeps alive until
+ * sw_server_destroy, or NULL (the library allocates it).  max_jobs (1..4096)
+ * bounds the active jobs.  hip_stream: the stream for all work, or NULL
+ * (the library creates one). */
+int sw_server_create(void *pool, size_t pool_bytes, int32_t max_jobs, void *hip_stream, sw_server **out);
+
+/* Queues a job; *job_id receives its id.  L, beta, J, init as for
+ * sw_create_ex; sweeps >= 1.  SW_ENOMEM if the job can never fit the pool. */
+int sw_server_submit(sw_server *server, int32_t L, double beta, double J, uint64_t seed,
+                     int32_t init, int64_t sweeps, int64_t *job_id);
+
+/* Admits queued jobs that fit, then runs up to n sweeps of the active set
+ * (fewer if it empties), retiring jobs as they finish and admitting queued
+ * ones into the memory they free.  Waits for the GPU before returning.
+ * done_ids[0..cap-1] receive the ids of the jobs that finished during the
+ * call; *ndone their number (which may exceed cap). */
+int sw_server_step(sw_server *server, int64_t n, int64_t *done_ids, int32_t cap, int32_t *ndone);
+
+/* State and progress of a job (SW_ERANGE for an unknown id). */
+int sw_server_job_info(sw_server *server, int64_t job_id, sw_job_info *info);
+
+/* Records first .. first+count-1 of an admitted job (sweeps run so far). */
+int sw_server_job_series(sw_server *server, int64_t job_id, int64_t first, int64_t count, sw_obs *out);
+
+/* Final spins of a finished job (n == L*L); SW_ESTATE before it is done. */
+int sw_server_job_spins(sw_server *server, int64_t job_id, int8_t *host, int64_t n);
+
+/* Forgets a finished or still queued job and frees its memory; SW_ESTATE for
+ * an active job. */
+int sw_server_release(sw_server *server, int64_t job_id);
+
+/* Queued and active job counts, pool bytes in use, and the site updates run
+ * since creation (any pointer may be NULL). */
+int sw_server_status(sw_server *server, int32_t *queued, int32_t *active, size_t *bytes_used,
+                     uint64_t *site_updates);
+
+/* Destroys the server and every job (waits for the stream first). */
+void sw_server_destroy(sw_server *server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,20 @@ class sw_config(ctypes.Structure):
     ]
 
 
+SW_JOB_QUEUED, SW_JOB_ACTIVE, SW_JOB_DONE = 0, 1, 2
+
+
+class sw_job_info(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64),
+        ("state", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("sweeps_done", ctypes.c_int64),
+        ("sweeps_total", ctypes.c_int64),
+        ("bytes", ctypes.c_uint64),
+    ]
+
+
 class SwError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"swmi error {code}: {msg}")
@@ -98,6 +112,17 @@ _SIGNATURES = {
     "sw_batch_threshold": (ctypes.c_uint32, [_P, ctypes.c_int32]),
     "sw_batch_tile": (ctypes.c_int32, [_P]),
     "sw_batch_destroy": (None, [_P]),
+    "sw_server_job_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
+    "sw_server_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.c_int32, _P, _P]),
+    "sw_server_submit": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                        ctypes.c_int32, ctypes.c_int64, _P]),
+    "sw_server_step": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_int32, _P]),
+    "sw_server_job_info": (ctypes.c_int, [_P, ctypes.c_int64, _P]),
+    "sw_server_job_series": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P]),
+    "sw_server_job_spins": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_int64]),
+    "sw_server_release": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "sw_server_status": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "sw_server_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -443,6 +468,87 @@ class Batch:
         h, self.handle = getattr(self, "handle", None), None
         if h:
             sw_batch_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """Serving runtime: jobs (L, beta, J, seed, sweeps) queue for room in a
+    device memory pool (a torch uint8 tensor of pool_bytes) and are advanced
+    together by the batched kernels; each job's results are those of a plain
+    sim run alone."""
+
+    def __init__(self, pool_bytes: int, max_jobs: int = 256, device=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("Server needs a ROCm GPU (torch.cuda.is_available() is False)")
+        dev = torch.device("cuda" if device is None else device)
+        self._pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=dev)
+        self._stream = torch.cuda.Stream(device=dev)
+        torch.cuda.current_stream(dev).synchronize()
+        h = ctypes.c_void_p()
+        _check(lib().sw_server_create(self._pool.data_ptr(), int(pool_bytes), max_jobs, self._stream.cuda_stream,
+                                      ctypes.byref(h)))
+        self.handle = h.value
+        self._done_buf = np.zeros(4096, dtype=np.int64)
+
+    @staticmethod
+    def job_bytes(L: int, sweeps: int) -> int:
+        return int(lib().sw_server_job_bytes(L, sweeps))
+
+    def submit(self, L: int, beta: float, J: float = 1.0, seed: int = 0, sweeps: int = 100,
+               init: int = SW_INIT_HOT) -> int:
+        jid = ctypes.c_int64()
+        _check(lib().sw_server_submit(self.handle, L, beta, J, seed, init, sweeps, ctypes.byref(jid)))
+        return jid.value
+
+    def step(self, n: int) -> list:
+        nd = ctypes.c_int32()
+        _check(lib().sw_server_step(self.handle, n, _ptr(self._done_buf), self._done_buf.size, ctypes.byref(nd)))
+        return self._done_buf[: min(nd.value, self._done_buf.size)].tolist()
+
+    def info(self, job: int) -> dict:
+        i = sw_job_info()
+        _check(lib().sw_server_job_info(self.handle, job, ctypes.byref(i)))
+        return {"id": i.id, "state": i.state, "L": i.L, "sweeps_done": i.sweeps_done,
+                "sweeps_total": i.sweeps_total, "bytes": i.bytes}
+
+    def series(self, job: int, first: int, count: int) -> np.ndarray:
+        out = np.zeros(count, dtype=OBS_DTYPE)
+        _check(lib().sw_server_job_series(self.handle, job, first, count, _ptr(out)))
+        return out
+
+    def spins(self, job: int) -> np.ndarray:
+        L = self.info(job)["L"]
+        out = np.empty(L * L, dtype=np.int8)
+        _check(lib().sw_server_job_spins(self.handle, job, _ptr(out), out.size))
+        return out
+
+    def release(self, job: int) -> None:
+        _check(lib().sw_server_release(self.handle, job))
+
+    def status(self) -> dict:
+        q, a = ctypes.c_int32(), ctypes.c_int32()
+        used, su = ctypes.c_size_t(), ctypes.c_uint64()
+        _check(lib().sw_server_status(self.handle, ctypes.byref(q), ctypes.byref(a), ctypes.byref(used),
+                                      ctypes.byref(su)))
+        return {"queued": q.value, "active": a.value, "bytes_used": used.value, "site_updates": su.value}
+
+    def close(self) -> None:
+        h, self.handle = getattr(self, "handle", None), None
+        if h:
+            lib().sw_server_destroy(h)
 
     def __del__(self):
         try:

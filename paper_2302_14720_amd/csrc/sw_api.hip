@@ -13,13 +13,26 @@
 #include <string>
 #include <vector>
 
-#include "sw_internal.h"
+#include "sw_host.h"
 
 using swmi::Dev;
+using swmi::Layout;
+using swmi::align_up;
+using swmi::bond_threshold;
+using swmi::fail;
+using swmi::hip_fail;
+using swmi::kAlign;
+using swmi::kDefaultRing;
+using swmi::layout_of;
+using swmi::make_dev;
+using swmi::resolve_tile;
+using swmi::validate;
+
+namespace swmi {
 
 namespace {
-
 thread_local std::string g_err;
+}
 
 int fail(int code, const std::string &msg) {
     g_err = msg;
@@ -30,16 +43,7 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(SW_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr)                                     \
-    do {                                                  \
-        hipError_t e_ = (expr);                           \
-        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-constexpr int64_t kDefaultRing = 4096;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+const std::string &last_error() { return g_err; }
 
 // Bond probability p = 1 - exp(-2 beta J) (Sec. 2.1, read with the factor 2J
 // that puts T_c at 2/ln(1+sqrt 2)), as a 32-bit threshold: P(bond) = T/2^32.
@@ -50,11 +54,6 @@ uint32_t bond_threshold(double beta, double J) {
     if (scaled >= 4294967296.0) return 0xFFFFFFFFu;
     return (uint32_t)scaled;
 }
-
-struct Layout {
-    size_t spins[2], parent[2], nk[2], key, nsize, rspin, edge, xb, tpart, gpart, acc, tdev, ring, labels,
-        dense, total;
-};
 
 int resolve_tile(const sw_config &c) {
     if (c.tile == 0) return (c.L % 64 == 0) ? 64 : 32;
@@ -145,7 +144,7 @@ Dev make_dev(const sw_config &c, char *base, const Layout &lo) {
     return d;
 }
 
-}  // namespace
+}  // namespace swmi
 
 struct sw_sim {
     sw_config cfg;
@@ -221,7 +220,7 @@ void ensure_graph(sw_sim *s) {
 
 extern "C" {
 
-const char *sw_last_error(void) { return g_err.c_str(); }
+const char *sw_last_error(void) { return swmi::last_error().c_str(); }
 
 int sw_config_init(sw_config *cfg, int32_t L, double beta, double J, uint64_t seed) {
     if (!cfg) return fail(SW_EINVAL, "cfg is NULL");
@@ -309,7 +308,7 @@ int sw_create_ex(const sw_config *cfg, void *dev_workspace, size_t ws_bytes, voi
     }
     rc = sw_reset(s, c.init);
     if (rc != SW_OK) {
-        const std::string msg = g_err;
+        const std::string msg = swmi::last_error();
         sw_destroy(s);
         return fail(rc, msg);
     }
@@ -538,8 +537,8 @@ constexpr int64_t kDefaultBatchRing = 1024;
 struct BatchPlan {
     std::vector<sw_config> cfg;
     std::vector<size_t> base;  // workspace offset of every replica
-    size_t devs, tmap, wmap, gmap, total;
-    uint32_t ntiles, nwmap, ngroups, tw;
+    size_t devs, tmap, wmap, gmap, umap, rmap, total;
+    uint32_t ntiles, nwmap, ngroups, nugroups, tw;
 };
 
 // Validates the replica table and lays out the batch workspace: the
@@ -556,7 +555,7 @@ int plan_batch(int32_t n, const int32_t *L, const double *beta, const double *J,
     p->cfg.assign((size_t)n, sw_config{});
     p->base.assign((size_t)n, 0);
     size_t off = 0;
-    p->ntiles = p->ngroups = 0;
+    p->ntiles = p->ngroups = p->nugroups = 0;
     for (int32_t r = 0; r < n; ++r) {
         sw_config &c = p->cfg[(size_t)r];
         sw_config_init(&c, L[r], beta[r], J[r], seed[r]);
@@ -564,13 +563,15 @@ int plan_batch(int32_t n, const int32_t *L, const double *beta, const double *J,
         c.tile = (int32_t)p->tw;
         c.ring = ring > 0 ? ring : kDefaultBatchRing;
         const int rc = validate(&c);
-        if (rc != SW_OK) return fail(rc, "replica " + std::to_string(r) + ": " + g_err);
+        if (rc != SW_OK) return fail(rc, "replica " + std::to_string(r) + ": " + swmi::last_error());
         const Layout lo = layout_of(c);
         p->base[(size_t)r] = off;
         off = align_up(off + lo.total);
         const uint32_t nt = (uint32_t)((c.L / p->tw) * (c.L / p->tw));
         p->ntiles += nt;
         p->ngroups += (nt + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
+        const uint32_t ngx = ((uint32_t)c.L / p->tw + swmi::kUG - 1u) / swmi::kUG;
+        p->nugroups += ngx * ngx;
     }
     p->nwmap = (p->ntiles + 3u) & ~3u;
     auto take = [&](size_t bytes) {
@@ -582,6 +583,8 @@ int plan_batch(int32_t n, const int32_t *L, const double *beta, const double *J,
     p->tmap = take((size_t)p->ntiles * 4);
     p->wmap = take((size_t)p->nwmap * 4);
     p->gmap = take((size_t)p->ngroups * 4);
+    p->umap = take((size_t)p->nugroups * 4);
+    p->rmap = take((size_t)n * 4);
     p->total = off;
     return SW_OK;
 }
@@ -698,14 +701,17 @@ int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const doubl
     char *base = (char *)b->ws;
     b->cfg = p.cfg;
     b->dev.resize(p.cfg.size());
-    std::vector<uint32_t> tmap, wmap, gmap;
+    std::vector<uint32_t> tmap, wmap, gmap, umap, rmap;
     tmap.reserve(p.ntiles);
     gmap.reserve(p.ngroups);
     for (size_t r = 0; r < p.cfg.size(); ++r) {
         b->dev[r] = make_dev(p.cfg[r], base + p.base[r], layout_of(p.cfg[r]));
+        rmap.push_back((uint32_t)r);
         const uint32_t tag = (uint32_t)r << swmi::kMapShift;
         for (uint32_t t = 0; t < b->dev[r].ntiles; ++t) tmap.push_back(tag | t);
         for (uint32_t g = 0; g < b->dev[r].ngroups; ++g) gmap.push_back(tag | g);
+        const uint32_t ngx = (b->dev[r].ntx + swmi::kUG - 1u) / swmi::kUG;
+        for (uint32_t g = 0; g < ngx * ngx; ++g) umap.push_back(tag | g);
     }
     wmap = tmap;
     wmap.resize(p.nwmap, swmi::kMapNone);
@@ -713,6 +719,9 @@ int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const doubl
     b->bd.tmap = (const uint32_t *)(base + p.tmap);
     b->bd.wmap = (const uint32_t *)(base + p.wmap);
     b->bd.gmap = (const uint32_t *)(base + p.gmap);
+    b->bd.umap = (const uint32_t *)(base + p.umap);
+    b->bd.rmap = (const uint32_t *)(base + p.rmap);
+    b->bd.nugroups = p.nugroups;
     b->bd.n = (uint32_t)p.cfg.size();
     b->bd.ntiles = p.ntiles;
     b->bd.nwmap = p.nwmap;
@@ -729,6 +738,10 @@ int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const doubl
         e = hipMemcpyAsync(base + p.wmap, wmap.data(), wmap.size() * 4, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(base + p.gmap, gmap.data(), gmap.size() * 4, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + p.umap, umap.data(), umap.size() * 4, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + p.rmap, rmap.data(), rmap.size() * 4, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         rc = hip_fail(e, "setting up the batch workspace");
@@ -737,7 +750,7 @@ int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const doubl
     }
     rc = sw_batch_reset(b, init);
     if (rc != SW_OK) {
-        const std::string msg = g_err;
+        const std::string msg = swmi::last_error();
         sw_batch_destroy(b);
         return fail(rc, msg);
     }

@@ -7,9 +7,12 @@
 //             tile's boundary clusters become "nodes" of a global graph;
 //             the spins of the previous sweep are resolved on the fly and
 //             measured (Sec. 2.5).
-//   k_union   union of nodes joined by bonds that cross tile edges, by
-//             lock-free union-find in global memory (lowest site wins).
-//   k_flatten point every node at its root; add node sizes into the roots.
+//   k_union   union of nodes joined by bonds that cross tile edges: first
+//             (k_ulocal) inside each 4x4 group of tiles in LDS, then, for
+//             the edges between groups, by lock-free union-find in global
+//             memory (the root is the node with the smaller index).
+//   k_flatten point every node at its root; add node sizes into the roots
+//             and reduce node keys to the cluster's smallest site.
 //   k_roots   new spin of each cross-tile cluster, cluster statistics.
 //   k_record  fold partial statistics into the per-sweep record ring.
 // Spins are double-buffered by sweep parity.  A written spin byte is either
@@ -31,6 +34,7 @@ constexpr int kTilePart = 32;         // int32 words of a per-tile partial
 constexpr int kGroupPart = 40;        // uint64 words of a per-group partial
 constexpr int kAccWords = 64;         // record accumulator + completion counter
 constexpr int kGroupTiles = 16;       // tiles per workgroup in k_flatten / k_roots
+constexpr uint32_t kUG = 4;           // side, in tiles, of a k_ulocal group
 
 // tile partial (int32 words)
 enum { TP_E = 0, TP_M = 1, TP_N = 2, TP_MAX = 3, TP_SQ = 4, TP_HIST = 5 };  // hist: 12 bins
@@ -81,7 +85,9 @@ struct BatchDev {
     const uint32_t *tmap;  // [ntiles] one entry per tile (k_tile, k_resolve)
     const uint32_t *wmap;  // [nwmap] one per wavefront of k_union, kMapNone-padded to 4
     const uint32_t *gmap;  // [ngroups] one per group of kGroupTiles tiles (k_flatten, k_roots)
-    uint32_t n, ntiles, nwmap, ngroups, tw;
+    const uint32_t *umap;  // [nugroups] one per kUG x kUG group of tiles (k_ulocal)
+    const uint32_t *rmap;  // [n] the replicas (indices into devs) this launch covers
+    uint32_t n, ntiles, nwmap, ngroups, nugroups, tw;
 };
 
 hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s);

@@ -118,20 +118,26 @@ __device__ __forceinline__ void lds_union2(uint32_t *par, uint32_t a, uint32_t b
         b = expected;
     }
 }
-// Union for the tile kernel, whose parent words carry other data in their
-// high halves (a work list while the unions run): parents are the low 16
-// bits, and the compare-and-swap that links the larger root under the
+// The tile kernel's parent words hold byte offsets into the LDS array (so a
+// parent is directly a load address) and carry other data in their high
+// halves (a work list while the unions run).
+__device__ __forceinline__ uint32_t *word_at(uint32_t *base, uint32_t off) {
+    return reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(base) + off);
+}
+
+// Union of the sets of the words at byte offsets a and b: parents are the
+// low 16 bits, and the compare-and-swap that links the larger root under the
 // smaller keeps the high half it read.  A failed swap (another lane linked
 // the root, or the high half changed) resumes from what it found.
 __device__ __forceinline__ void lds_union_lo(uint32_t *par, uint32_t a, uint32_t b) {
     while (true) {
-        uint32_t wa = lds_load(&par[a]), wb = lds_load(&par[b]);
+        uint32_t wa = lds_load(word_at(par, a)), wb = lds_load(word_at(par, b));
         uint32_t pa = wa & 0xFFFFu, pb = wb & 0xFFFFu;
         while (pa != a || pb != b) {
             a = pa;
             b = pb;
-            wa = lds_load(&par[a]);
-            wb = lds_load(&par[b]);
+            wa = lds_load(word_at(par, a));
+            wb = lds_load(word_at(par, b));
             pa = wa & 0xFFFFu;
             pb = wb & 0xFFFFu;
         }
@@ -140,13 +146,23 @@ __device__ __forceinline__ void lds_union_lo(uint32_t *par, uint32_t a, uint32_t
         const uint32_t hi = ahi ? a : b, lo = ahi ? b : a;
         uint32_t expected = ahi ? wa : wb;
         const uint32_t desired = (expected & 0xFFFF0000u) | lo;
-        if (__hip_atomic_compare_exchange_strong(&par[hi], &expected, desired, __ATOMIC_RELAXED,
+        if (__hip_atomic_compare_exchange_strong(word_at(par, hi), &expected, desired, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
             return;
         a = lo;
         b = expected & 0xFFFFu;
     }
 }
+
+// Root (byte offset) of the word at byte offset a once the unions are done.
+__device__ __forceinline__ uint32_t lds_root_b(uint32_t *par, uint32_t a) {
+    while (true) {
+        const uint32_t p = lds_load(word_at(par, a)) & 0xFFFFu;
+        if (p == a) return a;
+        a = p;
+    }
+}
+
 // Root of a once the unions are done (read-only; the high half of a root's
 // word may already hold its cluster size).
 __device__ __forceinline__ uint32_t lds_root(const uint32_t *par, uint32_t a) {
@@ -170,9 +186,11 @@ __device__ __forceinline__ void lds_union(uint32_t *par, uint32_t a, uint32_t b)
 }
 
 // ---------------------------------------------------------- global union-find
-// Nodes are ordered by key (their smallest site); a root is linked under the
-// root with the smaller key, so the final root of a cluster holds the
-// cluster's smallest site whatever order the unions run in.
+// A root is linked under the root with the smaller node index, so parents
+// always have smaller indices than their children and the structure stays
+// a forest whatever order the unions run in.  The cluster's smallest site
+// is gathered separately (k_flatten takes the minimum of the nodes' keys
+// into the root's key), so finds never read keys.
 __device__ __forceinline__ uint32_t g_load(uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -199,12 +217,12 @@ __device__ __forceinline__ uint32_t g_root(const uint32_t *par, uint32_t a) {
         a = p;
     }
 }
-__device__ __forceinline__ void g_union(uint32_t *par, const uint32_t *key, uint32_t a, uint32_t b) {
+__device__ __forceinline__ void g_union(uint32_t *par, uint32_t a, uint32_t b) {
     while (true) {
         a = g_find(par, a);
         b = g_find(par, b);
         if (a == b) return;
-        if (key[a] > key[b]) { const uint32_t tmp = a; a = b; b = tmp; }
+        if (a > b) { const uint32_t tmp = a; a = b; b = tmp; }
         uint32_t expected = b;
         if (__hip_atomic_compare_exchange_strong(&par[b], &expected, a, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
@@ -293,9 +311,9 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
 
     // One word per site, rows padded to PS = TW + 1 words so that the 16
     // sites a lane gathers at equal offsets fall in distinct banks.  Low 16
-    // bits: parent (a padded index).  High 16 bits: the union work list while
-    // the unions run, then the cluster size (roots), then the root's output
-    // byte.
+    // bits: parent, as the byte offset of its word.  High 16 bits: the union
+    // work list while the unions run, then the cluster size (roots), then
+    // the root's output byte.
     constexpr uint32_t PS = TW + 1;
     __shared__ uint32_t s_par[TW * PS];
     __shared__ Row s_up[TW + 1];
@@ -334,6 +352,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     const uint32_t east = ty * ntx + (tx + 1u == ntx ? 0u : tx + 1u);
     const uint32_t north = (ty + 1u == ntx ? 0u : ty + 1u) * ntx + tx;
     const uint32_t rowbase = ly * PS;  // padded index of the row's first site
+    const uint32_t rowoff = 4u * rowbase;  // its byte offset
     const uint32_t srow = ly * TW;     // site index of the row's first site
 
     // ---- issue the spin loads first, then build the node table
@@ -424,7 +443,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     const Row E0 = s_eb[ly];
     const Row B0 = (Row)~(Row)(E0 << 1);
     const uint32_t st = (uint32_t)(B0 >> x0) & 0xFFFFu;
-    const uint32_t rs0 = rowbase + hsb_le(B0, x0);
+    const uint32_t rs0 = rowoff + 4u * hsb_le(B0, x0);  // byte offset of the run start at x0
     uint32_t r = 0u;  // representative vertical bonds of this segment
     if (ly + 1u < (uint32_t)TW) {
         const Row V = s_nb[ly];
@@ -436,7 +455,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         uint32_t cur = rs0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            if ((st >> q) & 1u) cur = rowbase + x0 + (uint32_t)q;
+            if ((st >> q) & 1u) cur = rowoff + 4u * (x0 + (uint32_t)q);
             s_par[rowbase + x0 + q] = cur;
         }
         if (seg == RPT - 1u) s_par[rowbase + TW] = 0u;  // pad word: list slot only
@@ -467,7 +486,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         while (rr) {
             const uint32_t i = (uint32_t)__ffs((int)rr) - 1u;
             rr &= rr - 1u;
-            __hip_atomic_fetch_or(&s_par[w], (rowbase + x0 + i) << 16, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_or(&s_par[w], (rowoff + 4u * (x0 + i)) << 16, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_WORKGROUP);
             ++w;
         }
@@ -476,7 +495,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     for (uint32_t k = lane; k < nlist; k += 64u) {
         const uint32_t n = lds_load(&s_par[wbase + k]) >> 16;
         __hip_atomic_fetch_and(&s_par[wbase + k], 0xFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        lds_union_lo(s_par, n, n + PS);
+        lds_union_lo(s_par, n, n + 4u * PS);
     }
     __syncthreads();
 
@@ -496,18 +515,18 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
             const uint32_t i = (uint32_t)__ffs((int)m) - 1u;
             m &= m - 1u;
             const bool is_rs = (st >> i) & 1u;
-            const uint32_t n = is_rs ? rowbase + x0 + i : rs0;
-            const uint32_t root = lds_root(s_par, n);
+            const uint32_t n = is_rs ? rowoff + 4u * (x0 + i) : rs0;
+            const uint32_t root = lds_root_b(s_par, n);
             if (is_rs) {
                 if (root != n)
-                    __hip_atomic_store(&s_par[n], root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_store(word_at(s_par, n), root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 else
                     rootmask |= 1u << i;
             }
             const uint32_t len = (uint32_t)__ffs((int)(nxt >> (i + 1u)));
-            __hip_atomic_fetch_add(&s_par[root], len << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(word_at(s_par, root), len << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if ((em >> i) & 1u) {
-                const uint32_t rsite = root - root / PS;
+                const uint32_t rsite = root / 4u - root / (4u * PS);
                 atomicOr(&s_bf[rsite >> 5], 1u << (rsite & 31u));
             }
         }
@@ -575,7 +594,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
                     atomicAdd(&s_hist[bin], 1u);
                 if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
             }
-            s_par[root] = root | (code << 16);
+            s_par[root] = (4u * root) | (code << 16);
         }
     }
     __syncthreads();
@@ -593,9 +612,9 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         uint32_t cur = rs0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            if ((st >> q) & 1u) cur = rowbase + x0 + (uint32_t)q;
-            const uint32_t root = s_par[cur] & 0xFFFFu;
-            const uint32_t code = s_par[root] >> 16;
+            if ((st >> q) & 1u) cur = rowoff + 4u * (x0 + (uint32_t)q);
+            const uint32_t root = *word_at(s_par, cur) & 0xFFFFu;
+            const uint32_t code = *word_at(s_par, root) >> 16;
             out[q >> 2] |= code << (8 * (q & 3));
         }
     }
@@ -605,9 +624,9 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         uint32_t cur = rs0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            if ((st >> q) & 1u) cur = rowbase + x0 + (uint32_t)q;
-            const uint32_t root = s_par[cur] & 0xFFFFu;
-            const uint32_t rsite = root - root / PS;
+            if ((st >> q) & 1u) cur = rowoff + 4u * (x0 + (uint32_t)q);
+            const uint32_t root = *word_at(s_par, cur) & 0xFFFFu;
+            const uint32_t rsite = root / 4u - root / (4u * PS);
             const uint32_t code = (out[q >> 2] >> (8 * (q & 3))) & 0xFFu;
             lab[q] = (code >= 2u && code < 254u) ? (0x80000000u | (tile * kNodeSlots + code - 2u))
                                                  : (ty * TW + rsite / TW) * L + tx * TW + rsite % TW;
@@ -714,7 +733,10 @@ __device__ __forceinline__ void union_body(const Dev &d, const uint32_t tile) {
     const uint8_t *eg = d.edge + (size_t)tile * 4u * TW;
     const uint8_t *ege = d.edge + (size_t)east * 4u * TW;
     const uint8_t *egn = d.edge + (size_t)north * 4u * TW;
-    const uint64_t xe = d.xb[2u * tile], xn = d.xb[2u * tile + 1u];
+    // edges to a tile of the same kUG x kUG group were joined by k_ulocal
+    const uint64_t xe = ((tx % kUG) == kUG - 1u || tx + 1u == ntx) ? d.xb[2u * tile] : 0ull;
+    const uint64_t xn = ((ty % kUG) == kUG - 1u || ty + 1u == ntx) ? d.xb[2u * tile + 1u] : 0ull;
+    if ((xe | xn) == 0ull) return;
 
     auto one_pass = [&](uint64_t bits, uint32_t i, uint32_t a, uint32_t b) {
         const bool has = (bits >> i) & 1u;
@@ -722,7 +744,7 @@ __device__ __forceinline__ void union_body(const Dev &d, const uint32_t tile) {
         const uint32_t pb = __shfl_up(b, 1, 64);
         const int ph = __shfl_up((int)has, 1, 64);
         const bool dup = i > 0u && ph && pa == a && pb == b;
-        if (has && !dup) g_union(par, d.key, a, b);
+        if (has && !dup) g_union(par, a, b);
     };
     if constexpr (TW == 64) {
         one_pass(xe, lane, tile * kNodeSlots + eg[1 * TW + lane], east * kNodeSlots + ege[0 * TW + lane]);
@@ -734,6 +756,73 @@ __device__ __forceinline__ void union_body(const Dev &d, const uint32_t tile) {
         const uint32_t b = isn ? north * kNodeSlots + egn[2 * TW + i] : east * kNodeSlots + ege[0 * TW + i];
         one_pass(isn ? xn : xe, i, a, b);
     }
+}
+
+// =====================================================================
+// k_ulocal: the bonds between tiles of one kUG x kUG group join their nodes
+// in LDS (local index = tile-in-group * kNodeSlots + node, which orders
+// nodes as their global indices do, so the smaller index is the root in
+// both); every node then points at its group-local root in global memory,
+// and k_union only has the edges between groups left.
+// =====================================================================
+template <int TW>
+__device__ __forceinline__ void ulocal_body(const Dev &d, const uint32_t ugroup) {
+    constexpr uint32_t NG = kUG * kUG;
+    __shared__ uint32_t s_p[NG * kNodeSlots];
+    __shared__ uint32_t s_nk[NG];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t pc = (uint32_t)(*d.tdev & 1u);
+    const uint32_t ntx = d.ntx, ngx = (ntx + kUG - 1u) / kUG;
+    const uint32_t gx = ugroup % ngx, gy = ugroup / ngx;
+    auto tile_of = [&](uint32_t t) { return (gy * kUG + t / kUG) * ntx + gx * kUG + t % kUG; };
+    auto valid = [&](uint32_t t) { return gx * kUG + t % kUG < ntx && gy * kUG + t / kUG < ntx; };
+    if (tid < NG) s_nk[tid] = valid(tid) ? min(d.nk[pc][tile_of(tid)], 252u) : 0u;
+    for (uint32_t i = tid; i < NG * kNodeSlots; i += 256u) s_p[i] = i;
+    __syncthreads();
+
+    // tile-edges inside the group: E edges (lx < kUG-1), then N edges (ly < kUG-1)
+    constexpr uint32_t NE = (kUG - 1u) * kUG;
+    for (uint32_t f = tid; f < 2u * NE * TW; f += 256u) {
+        const uint32_t e = f / TW, i = f % TW;
+        const bool isn = e >= NE;
+        const uint32_t e2 = isn ? e - NE : e;
+        const uint32_t lx = isn ? e2 % kUG : e2 % (kUG - 1u), ly = isn ? e2 / kUG : e2 / (kUG - 1u);
+        const uint32_t ta = ly * kUG + lx, tb = isn ? ta + kUG : ta + 1u;
+        bool has = valid(ta) && valid(tb);
+        uint32_t a = 0u, b = 0u;
+        if (has) {
+            const uint32_t A = tile_of(ta), B = tile_of(tb);
+            has = (d.xb[2u * A + (isn ? 1u : 0u)] >> i) & 1u;
+            const uint8_t *ea = d.edge + (size_t)A * 4u * TW, *eb = d.edge + (size_t)B * 4u * TW;
+            a = ta * kNodeSlots + (isn ? ea[3 * TW + i] : ea[1 * TW + i]);
+            b = tb * kNodeSlots + (isn ? eb[2 * TW + i] : eb[0 * TW + i]);
+        }
+        // a run of bonds along the edge between the same two nodes needs one union
+        const uint32_t pa = __shfl_up(a, 1, 64), pb = __shfl_up(b, 1, 64);
+        const int ph = __shfl_up((int)has, 1, 64);
+        const bool dup = i > 0u && lane > 0u && ph && pa == a && pb == b;
+        if (has && !dup) lds_union(s_p, a, b);
+    }
+    __syncthreads();
+
+    uint32_t *par = d.parent[pc];
+    for (uint32_t li = tid; li < NG * kNodeSlots; li += 256u) {
+        const uint32_t t = li / kNodeSlots, k = li % kNodeSlots;
+        if (k >= s_nk[t]) continue;
+        const uint32_t r = lds_root(s_p, li);
+        if (r != li) par[tile_of(t) * kNodeSlots + k] = tile_of(r / kNodeSlots) * kNodeSlots + r % kNodeSlots;
+    }
+}
+
+template <int TW>
+__global__ __launch_bounds__(256) void k_ulocal(Dev d) {
+    ulocal_body<TW>(d, blockIdx.x);
+}
+
+template <int TW>
+__global__ __launch_bounds__(256) void k_ulocal_b(const Dev *devs, const uint32_t *map) {
+    const uint32_t e = map[blockIdx.x];
+    ulocal_body<TW>(devs[e >> kMapShift], e & kMapMask);
 }
 
 template <int TW>
@@ -750,39 +839,42 @@ __global__ __launch_bounds__(256) void k_union_b(const Dev *devs, const uint32_t
 
 // =====================================================================
 // k_flatten: every node points at its root; node sizes are summed into the
-// roots, first per workgroup in an LDS hash, then with one global atomic
-// per (workgroup, root).  The structure is final here, so finds only read
-// and the only stores are roots.
+// root's size and node keys (smallest sites) reduced to their minimum in the
+// root's key, first per workgroup in an LDS hash, then with one global
+// atomic of each kind per (workgroup, root).  The structure is final here,
+// so finds only read and the only stores are roots.
 // =====================================================================
 constexpr int kHashSlots = 4096;
 
-__device__ __forceinline__ void hash_add(uint32_t *hk, uint32_t *hv, uint32_t key, uint32_t val,
-                                         uint32_t *global_fallback) {
-    uint32_t h = (key * 2654435761u) >> 20;  // 12 bits
+__device__ __forceinline__ void hash_add(uint32_t *hk, uint32_t *hv, uint32_t *hm, uint32_t root, uint32_t size,
+                                         uint32_t key, const Dev &d) {
+    uint32_t h = (root * 2654435761u) >> 20;  // 12 bits
     for (int probe = 0; probe < 64; ++probe) {
         const uint32_t cur = lds_load(&hk[h]);
-        if (cur == key) {
-            atomicAdd(&hv[h], val);
-            return;
-        }
+        bool mine = cur == root;
         if (cur == kEmpty) {
-            const uint32_t old = atomicCAS(&hk[h], kEmpty, key);
-            if (old == kEmpty || old == key) {
-                atomicAdd(&hv[h], val);
-                return;
-            }
+            const uint32_t old = atomicCAS(&hk[h], kEmpty, root);
+            mine = old == kEmpty || old == root;
+        }
+        if (mine) {
+            atomicAdd(&hv[h], size);
+            atomicMin(&hm[h], key);
+            return;
         }
         h = (h + 1u) & (kHashSlots - 1);
     }
-    atomicAdd(&global_fallback[key], val);
+    atomicAdd(&d.nsize[root], size);
+    atomicMin(&d.key[root], key);
 }
 
 __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group) {
     __shared__ uint32_t hk[kHashSlots];
     __shared__ uint32_t hv[kHashSlots];
+    __shared__ uint32_t hm[kHashSlots];
     for (uint32_t i = threadIdx.x; i < (uint32_t)kHashSlots; i += 256u) {
         hk[i] = kEmpty;
         hv[i] = 0u;
+        hm[i] = kEmpty;
     }
     __syncthreads();
     const uint32_t pc = (uint32_t)(*d.tdev & 1u);
@@ -798,14 +890,17 @@ __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group)
             const uint32_t r = g_root(par, node);
             if (r != node) {
                 g_store(&par[node], r);
-                hash_add(hk, hv, r, d.nsize[node], d.nsize);
+                hash_add(hk, hv, hm, r, d.nsize[node], d.key[node], d);
             }
         }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < (uint32_t)kHashSlots; i += 256u) {
         const uint32_t k = hk[i];
-        if (k != kEmpty) atomicAdd(&d.nsize[k], hv[i]);
+        if (k != kEmpty) {
+            atomicAdd(&d.nsize[k], hv[i]);
+            atomicMin(&d.key[k], hm[i]);
+        }
     }
 }
 
@@ -1015,9 +1110,9 @@ __global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode
 
 // Batched record: one workgroup per replica folds all of that replica's
 // partials itself, so no cross-workgroup accumulator is needed.
-__global__ __launch_bounds__(256) void k_record_b(const Dev *devs, int mode) {
+__global__ __launch_bounds__(256) void k_record_b(const Dev *devs, const uint32_t *rmap, int mode) {
     __shared__ uint64_t s_acc[GP_END];
-    const Dev &d = devs[blockIdx.x];
+    const Dev &d = devs[rmap[blockIdx.x]];
     const uint32_t tid = threadIdx.x;
     if (tid < (uint32_t)GP_END) s_acc[tid] = 0u;
     __syncthreads();
@@ -1171,12 +1266,17 @@ hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
         else
             k_tile<32><<<d.ntiles, 64, 0, s>>>(d);
         break;
-    case 1:  // cross-tile unions
-        if (d.tw == 64)
+    case 1: {  // cross-tile unions: inside groups of tiles, then between groups
+        const uint32_t ngx = (d.ntx + kUG - 1u) / kUG;
+        if (d.tw == 64) {
+            k_ulocal<64><<<ngx * ngx, 256, 0, s>>>(d);
             k_union<64><<<(d.ntiles + 3) / 4, 256, 0, s>>>(d);
-        else
+        } else {
+            k_ulocal<32><<<ngx * ngx, 256, 0, s>>>(d);
             k_union<32><<<(d.ntiles + 3) / 4, 256, 0, s>>>(d);
+        }
         break;
+    }
     case 2:  // flatten + cluster sizes
         k_flatten<<<d.ngroups, 256, 0, s>>>(d);
         if (d.labels) k_relabel<<<grid_for(n, 256, 65536), 256, 0, s>>>(d);
@@ -1211,6 +1311,7 @@ hipError_t launch_resolve(const Dev &d, hipStream_t s) {
 }
 
 hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
+    if (b.n == 0) return hipSuccess;
     switch (stage) {
     case 0:
         if (b.tw == 64)
@@ -1219,10 +1320,13 @@ hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
             k_tile_b<32><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);
         break;
     case 1:
-        if (b.tw == 64)
+        if (b.tw == 64) {
+            k_ulocal_b<64><<<b.nugroups, 256, 0, s>>>(b.devs, b.umap);
             k_union_b<64><<<b.nwmap / 4, 256, 0, s>>>(b.devs, b.wmap);
-        else
+        } else {
+            k_ulocal_b<32><<<b.nugroups, 256, 0, s>>>(b.devs, b.umap);
             k_union_b<32><<<b.nwmap / 4, 256, 0, s>>>(b.devs, b.wmap);
+        }
         break;
     case 2:
         k_flatten_b<<<b.ngroups, 256, 0, s>>>(b.devs, b.gmap);
@@ -1231,7 +1335,7 @@ hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
         k_roots_b<<<b.ngroups, 256, 0, s>>>(b.devs, b.gmap);
         break;
     case 4:
-        k_record_b<<<b.n, 256, 0, s>>>(b.devs, 0);
+        k_record_b<<<b.n, 256, 0, s>>>(b.devs, b.rmap, 0);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1248,11 +1352,12 @@ hipError_t launch_batch_sweep(const BatchDev &b, hipStream_t s) {
 }
 
 hipError_t launch_batch_resolve(const BatchDev &b, hipStream_t s) {
+    if (b.n == 0) return hipSuccess;
     if (b.tw == 64)
         k_resolve_b<64><<<b.ntiles, 256, 0, s>>>(b.devs, b.tmap);
     else
         k_resolve_b<32><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);
-    k_record_b<<<b.n, 256, 0, s>>>(b.devs, 1);
+    k_record_b<<<b.n, 256, 0, s>>>(b.devs, b.rmap, 1);
     return hipGetLastError();
 }
 

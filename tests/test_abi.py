@@ -95,3 +95,11 @@ def test_batch_workspace_sizes_and_validation():
     rc = lib.sw_batch_create(0, None, None, None, None, 0, 0, None, 0, None, ctypes.byref(h))
     assert rc == sw.SW_EINVAL
     assert lib.sw_batch_size(None) == 0 and lib.sw_batch_next_sweep(None) == -1
+
+
+def test_server_job_bytes():
+    assert sw.Server.job_bytes(128, 100) > 2 * 128 * 128
+    assert sw.Server.job_bytes(128, 10000) > sw.Server.job_bytes(128, 100)
+    assert sw.Server.job_bytes(100, 100) == 0
+    assert sw.Server.job_bytes(128, 0) == 0
+    assert sw.sw_last_error is not None

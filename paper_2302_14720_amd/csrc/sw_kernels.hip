@@ -844,11 +844,11 @@ __global__ __launch_bounds__(256) void k_union_b(const Dev *devs, const uint32_t
 // atomic of each kind per (workgroup, root).  The structure is final here,
 // so finds only read and the only stores are roots.
 // =====================================================================
-constexpr int kHashSlots = 4096;
+constexpr int kHashSlots = 2048;
 
 __device__ __forceinline__ void hash_add(uint32_t *hk, uint32_t *hv, uint32_t *hm, uint32_t root, uint32_t size,
                                          uint32_t key, const Dev &d) {
-    uint32_t h = (root * 2654435761u) >> 20;  // 12 bits
+    uint32_t h = (root * 2654435761u) >> 21;  // 11 bits
     for (int probe = 0; probe < 64; ++probe) {
         const uint32_t cur = lds_load(&hk[h]);
         bool mine = cur == root;
@@ -1022,22 +1022,45 @@ __global__ __launch_bounds__(256) void k_roots_b(const Dev *devs, const uint32_t
 // (mode 1, end of k_resolve) into the record ring; the last workgroup to
 // finish writes the record and clears the accumulator.
 // =====================================================================
-// One partial into the workgroup's LDS accumulator.
-__device__ __forceinline__ void record_add(const Dev &d, uint32_t item, int mode, uint64_t *s_acc) {
+// Folds partials [begin, end) into the workgroup's LDS accumulator.  Group
+// partials (mode 0): thread t sums field t % 64 over every fourth partial,
+// so each accumulator word takes four LDS atomics.  Tile partials (mode 1,
+// energy and magnetisation only): per-thread sums, reduced per wavefront.
+constexpr uint32_t kRecordGroups = 64;   // group partials per k_record workgroup
+constexpr uint32_t kRecordTiles = 2048;  // tile partials per k_record workgroup
+
+__device__ __forceinline__ void record_fold(const Dev &d, uint32_t begin, uint32_t end, int mode, uint64_t *s_acc) {
+    const uint32_t tid = threadIdx.x;
     unsigned long long *a = reinterpret_cast<unsigned long long *>(s_acc);
     if (mode == 0) {
-        const uint64_t *gp = d.gpart + (size_t)item * kGroupPart;
-        atomicAdd(&a[GP_N], (unsigned long long)gp[GP_N]);
-        atomicMax(&a[GP_MAX], (unsigned long long)gp[GP_MAX]);
-        atomicAdd(&a[GP_SQ], (unsigned long long)gp[GP_SQ]);
-        atomicAdd(&a[GP_E], (unsigned long long)gp[GP_E]);
-        atomicAdd(&a[GP_M], (unsigned long long)gp[GP_M]);
-        for (int b = 0; b < 33; ++b)
-            if (gp[GP_HIST + b]) atomicAdd(&a[GP_HIST + b], (unsigned long long)gp[GP_HIST + b]);
+        const uint32_t f = tid & 63u, sub = tid >> 6;
+        if (f < (uint32_t)GP_END) {
+            uint64_t v = 0;
+            for (uint32_t item = begin + sub; item < end; item += 4u) {
+                const uint64_t x = d.gpart[(size_t)item * kGroupPart + f];
+                v = f == (uint32_t)GP_MAX ? max(v, x) : v + x;
+            }
+            if (f == (uint32_t)GP_MAX)
+                atomicMax(&a[f], (unsigned long long)v);
+            else if (v)
+                atomicAdd(&a[f], (unsigned long long)v);
+        }
     } else {
-        const int32_t *tp = d.tpart + (size_t)item * kTilePart;
-        atomicAdd(&a[GP_E], (unsigned long long)(int64_t)tp[TP_E]);
-        atomicAdd(&a[GP_M], (unsigned long long)(int64_t)tp[TP_M]);
+        int64_t e = 0, m = 0;
+        for (uint32_t item = begin + tid; item < end; item += 256u) {
+            const int32_t *tp = d.tpart + (size_t)item * kTilePart;
+            e += tp[TP_E];
+            m += tp[TP_M];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            e += __shfl_xor(e, o, 64);
+            m += __shfl_xor(m, o, 64);
+        }
+        if ((tid & 63u) == 0u) {
+            atomicAdd(&a[GP_E], (unsigned long long)e);
+            atomicAdd(&a[GP_M], (unsigned long long)m);
+        }
     }
 }
 
@@ -1077,8 +1100,9 @@ __global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode
     const uint32_t tid = threadIdx.x;
     if (tid < (uint32_t)GP_END) s_acc[tid] = 0u;
     __syncthreads();
-    const uint32_t item = blockIdx.x * 256u + tid;
-    if (item < nitems) record_add(d, item, mode, s_acc);
+    const uint32_t per = mode == 0 ? kRecordGroups : kRecordTiles;
+    const uint32_t begin = blockIdx.x * per;
+    record_fold(d, begin, min(begin + per, nitems), mode, s_acc);
     __syncthreads();
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(d.acc);
     if (tid < (uint32_t)GP_END && s_acc[tid] != 0u) {
@@ -1116,8 +1140,7 @@ __global__ __launch_bounds__(256) void k_record_b(const Dev *devs, const uint32_
     const uint32_t tid = threadIdx.x;
     if (tid < (uint32_t)GP_END) s_acc[tid] = 0u;
     __syncthreads();
-    const uint32_t nitems = mode == 0 ? d.ngroups : d.ntiles;
-    for (uint32_t item = tid; item < nitems; item += 256u) record_add(d, item, mode, s_acc);
+    record_fold(d, 0u, mode == 0 ? d.ngroups : d.ntiles, mode, s_acc);
     __syncthreads();
     record_write(d, s_acc, mode);
 }
@@ -1285,7 +1308,7 @@ hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
         k_roots<<<d.ngroups, 256, 0, s>>>(d);
         break;
     case 4:  // record
-        k_record<<<(d.ngroups + 255) / 256, 256, 0, s>>>(d, d.ngroups, 0);
+        k_record<<<(d.ngroups + kRecordGroups - 1) / kRecordGroups, 256, 0, s>>>(d, d.ngroups, 0);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1306,7 +1329,7 @@ hipError_t launch_resolve(const Dev &d, hipStream_t s) {
         k_resolve<64><<<d.ntiles, 256, 0, s>>>(d);
     else
         k_resolve<32><<<d.ntiles, 64, 0, s>>>(d);
-    k_record<<<(d.ntiles + 255) / 256, 256, 0, s>>>(d, d.ntiles, 1);
+    k_record<<<(d.ntiles + kRecordTiles - 1) / kRecordTiles, 256, 0, s>>>(d, d.ntiles, 1);
     return hipGetLastError();
 }
 

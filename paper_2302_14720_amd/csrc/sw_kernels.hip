@@ -332,7 +332,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     // masks, which are dead once the unions are done
     __shared__ uint32_t s_node_own[TW == 64 ? 1 : 4 * TW];
     uint32_t *const s_node = TW == 64 ? reinterpret_cast<uint32_t *>(s_ebnb) : s_node_own;
-    __shared__ int32_t s_red[NWAVE][8];
+    __shared__ int32_t s_red[NWAVE][4];
     __shared__ uint32_t s_k;
 
     const uint32_t tid = threadIdx.x;
@@ -499,17 +499,13 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     }
     __syncthreads();
 
-    // ---- cluster sizes and edge contact.  A piece is the part of a run
-    // inside this lane's 16 sites; every piece adds its length to the root
-    // of its run, pieces on the tile edge mark the root, and every run start
-    // is pointed at its root.
+    // ---- cluster sizes.  A piece is the part of a run inside this lane's 16
+    // sites; every piece adds its length to the root of its run, and every
+    // run start is pointed at its root.
     uint32_t rootmask = 0u;
     {
         const uint32_t pst = st | 1u;  // piece starts
         const uint32_t nxt = pst | 0x10000u;
-        uint32_t em = (ly == 0u || ly == (uint32_t)TW - 1u) ? pst : 0u;
-        if (seg == 0u) em |= 1u;
-        if (seg == RPT - 1u) em |= 1u << (31u - (uint32_t)__clz((int)pst));
         uint32_t m = pst;
         while (m) {
             const uint32_t i = (uint32_t)__ffs((int)m) - 1u;
@@ -525,11 +521,21 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
             }
             const uint32_t len = (uint32_t)__ffs((int)(nxt >> (i + 1u)));
             __hip_atomic_fetch_add(word_at(s_par, root), len << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if ((em >> i) & 1u) {
-                const uint32_t rsite = root / 4u - root / (4u * PS);
-                atomicOr(&s_bf[rsite >> 5], 1u << (rsite & 31u));
-            }
         }
+    }
+    __syncthreads();
+
+    // ---- clusters that touch the tile edge: one edge site per thread marks
+    // its root (run starts now point at their roots)
+    for (uint32_t e = tid; e < 4u * (TW - 1u); e += NT) {
+        const uint32_t side = e / (TW - 1u), j = e % (TW - 1u);
+        // S row x = j, N row x = j + 1, W column y = j + 1, E column y = j
+        const uint32_t y = side == 0u ? 0u : side == 1u ? TW - 1u : side == 2u ? j + 1u : j;
+        const uint32_t x = side == 0u ? j : side == 1u ? j + 1u : side == 2u ? 0u : TW - 1u;
+        const uint32_t rs = s_par[y * PS + x] & 0xFFFFu;
+        const uint32_t root = *word_at(s_par, rs) & 0xFFFFu;
+        const uint32_t rsite = root / 4u - root / (4u * PS);
+        atomicOr(&s_bf[rsite >> 5], 1u << (rsite & 31u));
     }
     __syncthreads();
 
@@ -564,7 +570,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     // ---- roots: output byte into the root's word; node entries staged in
     // LDS; interior-cluster statistics (size classes 0-2 packed in one
     // register, 10 bits each)
-    uint32_t n_int = 0u, max_int = 0u, sq_int = 0u, hpk = 0u;
+    uint32_t max_int = 0u, sq_int = 0u, hpk = 0u;
     {
         const uint32_t sbase = srow + x0;  // site index of this lane's first site
         const uint32_t bfw = s_bf[sbase >> 5];
@@ -584,7 +590,6 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
                 code = 2u + k;
             } else {
                 code = ((fl >> q) & 1u) ? 0xFFu : 0x01u;
-                ++n_int;
                 max_int = max(max_int, S);
                 sq_int += S * S;
                 const uint32_t bin = 31u - (uint32_t)__clz((int)S);
@@ -649,43 +654,39 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
             *reinterpret_cast<uint4 *>(eg + 3 * TW + x0) =
                 make_uint4(out[0] - 0x02020202u, out[1] - 0x02020202u, out[2] - 0x02020202u, out[3] - 0x02020202u);
     }
-    uint32_t h0 = hpk & 0x3FFu, h1 = (hpk >> 10) & 0x3FFu, h2 = hpk >> 20;
+    // energy and magnetisation packed as (e + 32) | (m + 16) << 16 per lane:
+    // the wavefront sums stay below 2^13 and 2^12
+    uint32_t em = (uint32_t)(e_part + 32) | ((uint32_t)(m_part + 16) << 16);
 
     // ---- workgroup reductions -> tile partial
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        e_part += __shfl_xor(e_part, o, 64);
-        m_part += __shfl_xor(m_part, o, 64);
-        n_int += __shfl_xor(n_int, o, 64);
+        em += __shfl_xor(em, o, 64);
+        hpk += __shfl_xor(hpk, o, 64);
         max_int = max(max_int, (uint32_t)__shfl_xor((int)max_int, o, 64));
         sq_int += __shfl_xor(sq_int, o, 64);
-        h0 += __shfl_xor(h0, o, 64);
-        h1 += __shfl_xor(h1, o, 64);
-        h2 += __shfl_xor(h2, o, 64);
     }
     if ((tid & 63u) == 0u) {
-        s_red[tid >> 6][0] = e_part;
-        s_red[tid >> 6][1] = m_part;
-        s_red[tid >> 6][2] = (int32_t)n_int;
-        s_red[tid >> 6][3] = (int32_t)max_int;
-        s_red[tid >> 6][4] = (int32_t)sq_int;
-        s_red[tid >> 6][5] = (int32_t)h0;
-        s_red[tid >> 6][6] = (int32_t)h1;
-        s_red[tid >> 6][7] = (int32_t)h2;
+        s_red[tid >> 6][0] = (int32_t)em;
+        s_red[tid >> 6][1] = (int32_t)hpk;
+        s_red[tid >> 6][2] = (int32_t)max_int;
+        s_red[tid >> 6][3] = (int32_t)sq_int;
     }
     __syncthreads();
     if (tid == 0u) {
-        int32_t e = 0, m = 0, n = 0, mx = 0, sq = 0, b0 = 0, b1 = 0, b2 = 0;
+        int32_t e = 0, m = 0, mx = 0, sq = 0, b0 = 0, b1 = 0, b2 = 0;
         for (int w = 0; w < NWAVE; ++w) {
-            e += s_red[w][0];
-            m += s_red[w][1];
-            n += s_red[w][2];
-            mx = max(mx, s_red[w][3]);
-            sq += s_red[w][4];
-            b0 += s_red[w][5];
-            b1 += s_red[w][6];
-            b2 += s_red[w][7];
+            const uint32_t ew = (uint32_t)s_red[w][0], hw = (uint32_t)s_red[w][1];
+            e += (int32_t)(ew & 0xFFFFu) - 32 * 64;
+            m += (int32_t)(ew >> 16) - 16 * 64;
+            b0 += (int32_t)(hw & 0x3FFu);
+            b1 += (int32_t)((hw >> 10) & 0x3FFu);
+            b2 += (int32_t)(hw >> 20);
+            mx = max(mx, s_red[w][2]);
+            sq += s_red[w][3];
         }
+        int32_t n = b0 + b1 + b2;
+        for (int b = 3; b < 12; ++b) n += (int32_t)s_hist[b];
         int32_t *tp = d.tpart + (size_t)tile * kTilePart;
         tp[TP_E] = e;
         tp[TP_M] = m;

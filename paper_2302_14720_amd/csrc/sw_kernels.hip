@@ -217,10 +217,20 @@ __device__ __forceinline__ uint32_t g_root(const uint32_t *par, uint32_t a) {
         a = p;
     }
 }
+// Both finds advance together (their loads overlap), each with path
+// halving: a node is re-pointed at its grandparent, which is an ancestor
+// whatever other unions did meanwhile.
 __device__ __forceinline__ void g_union(uint32_t *par, uint32_t a, uint32_t b) {
     while (true) {
-        a = g_find(par, a);
-        b = g_find(par, b);
+        while (true) {
+            const uint32_t pa = g_load(&par[a]), pb = g_load(&par[b]);
+            if (pa == a && pb == b) break;
+            const uint32_t ga = g_load(&par[pa]), gb = g_load(&par[pb]);
+            if (ga != pa) g_store(&par[a], ga);
+            if (gb != pb) g_store(&par[b], gb);
+            a = ga;
+            b = gb;
+        }
         if (a == b) return;
         if (a > b) { const uint32_t tmp = a; a = b; b = tmp; }
         uint32_t expected = b;
@@ -724,38 +734,31 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile_b(const Dev *devs, const u
 // on both sides (Sec. 2.3, global part).  One wavefront per tile.
 // =====================================================================
 template <int TW>
-__device__ __forceinline__ void union_body(const Dev &d, const uint32_t tile) {
+__device__ __forceinline__ void union_body(const Dev &d, const uint32_t tile, const uint32_t dir) {
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t ntx = d.ntx, tx = tile % ntx, ty = tile / ntx;
+    // edges to a tile of the same kUG x kUG group were joined by k_ulocal
+    const bool glob = dir == 0u ? ((tx % kUG) == kUG - 1u || tx + 1u == ntx)
+                                : ((ty % kUG) == kUG - 1u || ty + 1u == ntx);
+    if (!glob) return;
+    const uint64_t bits = d.xb[2u * tile + dir];
+    if (bits == 0ull) return;
     const uint32_t pc = (uint32_t)(*d.tdev & 1u);
     uint32_t *par = d.parent[pc];
-    const uint32_t ntx = d.ntx, tx = tile % ntx, ty = tile / ntx;
-    const uint32_t east = ty * ntx + (tx + 1u == ntx ? 0u : tx + 1u);
-    const uint32_t north = (ty + 1u == ntx ? 0u : ty + 1u) * ntx + tx;
+    const uint32_t nb = dir == 0u ? ty * ntx + (tx + 1u == ntx ? 0u : tx + 1u)
+                                  : (ty + 1u == ntx ? 0u : ty + 1u) * ntx + tx;
     const uint8_t *eg = d.edge + (size_t)tile * 4u * TW;
-    const uint8_t *ege = d.edge + (size_t)east * 4u * TW;
-    const uint8_t *egn = d.edge + (size_t)north * 4u * TW;
-    // edges to a tile of the same kUG x kUG group were joined by k_ulocal
-    const uint64_t xe = ((tx % kUG) == kUG - 1u || tx + 1u == ntx) ? d.xb[2u * tile] : 0ull;
-    const uint64_t xn = ((ty % kUG) == kUG - 1u || ty + 1u == ntx) ? d.xb[2u * tile + 1u] : 0ull;
-    if ((xe | xn) == 0ull) return;
-
-    auto one_pass = [&](uint64_t bits, uint32_t i, uint32_t a, uint32_t b) {
+    const uint8_t *egb = d.edge + (size_t)nb * 4u * TW;
+    // one lane per edge position (two passes of 32 lanes for 32-wide tiles)
+    for (uint32_t i = lane; i < (uint32_t)TW; i += 64u) {
         const bool has = (bits >> i) & 1u;
-        const uint32_t pa = __shfl_up(a, 1, 64);
-        const uint32_t pb = __shfl_up(b, 1, 64);
+        const uint32_t a = tile * kNodeSlots + (dir == 0u ? eg[1 * TW + i] : eg[3 * TW + i]);
+        const uint32_t b = nb * kNodeSlots + (dir == 0u ? egb[0 * TW + i] : egb[2 * TW + i]);
+        // a run of bonds along the edge between the same two nodes needs one union
+        const uint32_t pa = __shfl_up(a, 1, 64), pb = __shfl_up(b, 1, 64);
         const int ph = __shfl_up((int)has, 1, 64);
         const bool dup = i > 0u && ph && pa == a && pb == b;
         if (has && !dup) g_union(par, a, b);
-    };
-    if constexpr (TW == 64) {
-        one_pass(xe, lane, tile * kNodeSlots + eg[1 * TW + lane], east * kNodeSlots + ege[0 * TW + lane]);
-        one_pass(xn, lane, tile * kNodeSlots + eg[3 * TW + lane], north * kNodeSlots + egn[2 * TW + lane]);
-    } else {
-        const uint32_t i = lane & 31u;
-        const bool isn = lane >= 32u;
-        const uint32_t a = tile * kNodeSlots + (isn ? eg[3 * TW + i] : eg[1 * TW + i]);
-        const uint32_t b = isn ? north * kNodeSlots + egn[2 * TW + i] : east * kNodeSlots + ege[0 * TW + i];
-        one_pass(isn ? xn : xe, i, a, b);
     }
 }
 
@@ -826,16 +829,19 @@ __global__ __launch_bounds__(256) void k_ulocal_b(const Dev *devs, const uint32_
     ulocal_body<TW>(devs[e >> kMapShift], e & kMapMask);
 }
 
+// One wavefront per (tile, direction): wave w of the launch takes tile w / 2
+// and its E (w even) or N (w odd) edge.
 template <int TW>
 __global__ __launch_bounds__(256) void k_union(Dev d) {
-    const uint32_t tile = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (tile < d.ntiles) union_body<TW>(d, tile);
+    const uint32_t w = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (w / 2u < d.ntiles) union_body<TW>(d, w / 2u, w & 1u);
 }
 
 template <int TW>
 __global__ __launch_bounds__(256) void k_union_b(const Dev *devs, const uint32_t *map) {
-    const uint32_t e = map[blockIdx.x * 4u + (threadIdx.x >> 6)];
-    if (e != kMapNone) union_body<TW>(devs[e >> kMapShift], e & kMapMask);
+    const uint32_t w = blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint32_t e = map[w / 2u];
+    if (e != kMapNone) union_body<TW>(devs[e >> kMapShift], e & kMapMask, w & 1u);
 }
 
 // =====================================================================
@@ -882,17 +888,47 @@ __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group)
     uint32_t *par = d.parent[pc];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t g0 = group * (uint32_t)kGroupTiles;
-    for (uint32_t tt = wv; tt < (uint32_t)kGroupTiles; tt += 4u) {
-        const uint32_t tile = g0 + tt;
-        if (tile >= d.ntiles) break;
-        const uint32_t K = min(d.nk[pc][tile], 252u);
-        for (uint32_t k = lane; k < K; k += 64u) {
-            const uint32_t node = tile * kNodeSlots + k;
-            const uint32_t r = g_root(par, node);
-            if (r != node) {
-                g_store(&par[node], r);
-                hash_add(hk, hv, hm, r, d.nsize[node], d.key[node], d);
+    // wavefront wv owns tiles g0 + wv + 4q (q < TPW), i.e. TPW x kNodeSlots
+    // slots; each lane chases the roots of up to 8 slots at once, one level
+    // per round, so their loads overlap
+    constexpr uint32_t TPW = kGroupTiles / 4;
+    uint32_t nkq[TPW];
+#pragma unroll
+    for (uint32_t q = 0; q < TPW; ++q) {
+        const uint32_t tile = g0 + wv + 4u * q;
+        const uint32_t v = d.nk[pc][min(tile, d.ntiles - 1u)];  // issued unconditionally
+        nkq[q] = tile < d.ntiles ? min(v, 252u) : 0u;
+    }
+    constexpr uint32_t kChase = 8;
+#pragma unroll
+    for (uint32_t m0 = 0; m0 < TPW * kNodeSlots / 64u; m0 += kChase) {
+        uint32_t nd[kChase], r[kChase];
+#pragma unroll
+        for (uint32_t j = 0; j < kChase; ++j) {
+            const uint32_t slot = lane + 64u * (m0 + j), q = slot / kNodeSlots, k = slot % kNodeSlots;
+            nd[j] = k < nkq[q] ? (g0 + wv + 4u * q) * kNodeSlots + k : kEmpty;
+            r[j] = nd[j];
+        }
+        bool more = true;
+        while (more) {
+            // all loads first (an empty slot reads node 0 and ignores it)
+            uint32_t p[kChase];
+#pragma unroll
+            for (uint32_t j = 0; j < kChase; ++j)
+                p[j] = __hip_atomic_load(&par[r[j] == kEmpty ? 0u : r[j]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            more = false;
+#pragma unroll
+            for (uint32_t j = 0; j < kChase; ++j) {
+                const uint32_t q = r[j] == kEmpty ? kEmpty : p[j];
+                more |= q != r[j];
+                r[j] = q;
             }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kChase; ++j) {
+            if (nd[j] == kEmpty || r[j] == nd[j]) continue;
+            g_store(&par[nd[j]], r[j]);
+            hash_add(hk, hv, hm, r[j], d.nsize[nd[j]], d.key[nd[j]], d);
         }
     }
     __syncthreads();
@@ -1294,10 +1330,10 @@ hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
         const uint32_t ngx = (d.ntx + kUG - 1u) / kUG;
         if (d.tw == 64) {
             k_ulocal<64><<<ngx * ngx, 256, 0, s>>>(d);
-            k_union<64><<<(d.ntiles + 3) / 4, 256, 0, s>>>(d);
+            k_union<64><<<(d.ntiles + 1) / 2, 256, 0, s>>>(d);
         } else {
             k_ulocal<32><<<ngx * ngx, 256, 0, s>>>(d);
-            k_union<32><<<(d.ntiles + 3) / 4, 256, 0, s>>>(d);
+            k_union<32><<<(d.ntiles + 1) / 2, 256, 0, s>>>(d);
         }
         break;
     }
@@ -1346,10 +1382,10 @@ hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
     case 1:
         if (b.tw == 64) {
             k_ulocal_b<64><<<b.nugroups, 256, 0, s>>>(b.devs, b.umap);
-            k_union_b<64><<<b.nwmap / 4, 256, 0, s>>>(b.devs, b.wmap);
+            k_union_b<64><<<b.nwmap / 2, 256, 0, s>>>(b.devs, b.wmap);
         } else {
             k_ulocal_b<32><<<b.nugroups, 256, 0, s>>>(b.devs, b.umap);
-            k_union_b<32><<<b.nwmap / 4, 256, 0, s>>>(b.devs, b.wmap);
+            k_union_b<32><<<b.nwmap / 2, 256, 0, s>>>(b.devs, b.wmap);
         }
         break;
     case 2:

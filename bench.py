@@ -180,6 +180,38 @@ def serving(args):
     }
 
 
+def label_equivalence(args, tile_rate):
+    """The paper's own cluster formation (iterated label equivalence in
+    global memory, one cooperative kernel) against the tile pipeline: the
+    same sweeps, bit for bit, at the paper's 512^2 / beta = 0.4 and at the
+    headline lattice."""
+    import paper_2302_14720_amd as sw
+
+    out = {}
+    for L, beta, seed in ((512, 0.4, 7), (args.L, BETA_C, args.seed)):
+        res = {}
+        for name, flags in (("label_equivalence", sw.SW_FLAG_LABEL_EQUIV), ("tile", 0)):
+            if name == "tile" and L == args.L:
+                res[name] = tile_rate
+                continue
+            s = sw.Sim(L, beta, 1.0, seed, flags=flags)
+            s.sweep(3)
+            s.sync()
+            t0 = time.perf_counter()
+            s.sweep(args.le_steps)
+            s.sync()
+            dt = time.perf_counter() - t0
+            res[name] = L * L * args.le_steps / dt
+            if flags:
+                res["passes_last_sweep"] = s.label_passes
+            s.close()
+        res["tile_over_label_equivalence"] = res["tile"] / res["label_equivalence"]
+        out[f"L{L}_beta{beta:.4f}"] = res
+        print(f"[bench] label equivalence L={L}: {res}", file=sys.stderr, flush=True)
+    out["unit"] = "site-updates/s"
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +230,8 @@ def main() -> int:
                     help="timed sweeps of the same replicas as plain sims, one sw_sweep per replica per sweep")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--serve-jobs", type=int, default=48, help="jobs of the serving leg (0 = skip)")
+    ap.add_argument("--le-steps", type=int, default=10,
+                    help="timed sweeps of the label-equivalence comparison (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the serving leg, jobs/s")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for "
@@ -319,6 +353,7 @@ def main() -> int:
                        "first_sweep_max_cluster": int(crec["max_cluster"])},
         "batched": None if args.no_batched else batched_vs_plain(args),
         "serving": serving(args) if args.serve_jobs > 0 else None,
+        "label_equivalence": label_equivalence(args, value) if args.le_steps > 0 else None,
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on one L=%d sweep" % L, file=sys.stderr, flush=True)

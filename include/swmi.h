@@ -59,6 +59,7 @@ extern "C" {
 
 #define SW_FLAG_LABELS 1u      /* keep the canonical labels of the last sweep */
 #define SW_FLAG_DENSE_HIST 2u  /* keep the exact cluster-size histogram       */
+#define SW_FLAG_LABEL_EQUIV 4u /* label clusters the paper's way (see below)  */
 
 typedef struct sw_sim sw_sim;
 
@@ -169,6 +170,22 @@ int sw_set_spins(sw_sim *sim, const int8_t *host, int64_t n, uint64_t next_sweep
  * clusters to host memory, n == N.  Needs SW_FLAG_LABELS and a completed
  * sweep. */
 int sw_get_labels(sw_sim *sim, uint32_t *host, int64_t n);
+
+/* Sims created with SW_FLAG_LABEL_EQUIV form clusters as the paper does
+ * (Sec. 2.3, after Kalentev et al.): every site starts with its own index
+ * as label; a scan pass points the entry of each site's label at the
+ * smallest label among its bonded neighbours, an analysis pass makes every
+ * site take the label at the end of its chain of references, and the two
+ * repeat until a scan changes nothing -- all passes inside one cooperative
+ * kernel that polls a device-side flag (the paper used a dynamic-
+ * parallelism kernel for this, Sec. 5).  Labels, spins and records are
+ * identical to the default path (the tile pipeline); it is slower and
+ * exists to compare the two designs.  Labels are always kept (no need for
+ * SW_FLAG_LABELS); the tile option is ignored.
+ * sw_label_passes returns the number of scan/analysis passes of the last
+ * sweep (waits for the stream), -2 if that sweep stopped at the pass limit
+ * (65,536) without converging, -1 for a sim of the default path. */
+int32_t sw_label_passes(sw_sim *sim);
 
 /* The bond threshold T of this sim (so callers can check it). */
 uint32_t sw_threshold(const sw_sim *sim);

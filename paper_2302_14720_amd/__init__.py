@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libswmi.so")
 
 SW_OK, SW_EINVAL, SW_ERANGE, SW_ENOMEM, SW_EHIP, SW_ESTATE = 0, -1, -2, -3, -4, -5
 SW_INIT_HOT, SW_INIT_COLD = 0, 1
-SW_FLAG_LABELS, SW_FLAG_DENSE_HIST = 1, 2
+SW_FLAG_LABELS, SW_FLAG_DENSE_HIST, SW_FLAG_LABEL_EQUIV = 1, 2, 4
 
 # Layout of ``sw_obs`` (swmi.h).
 OBS_DTYPE = np.dtype(
@@ -92,6 +92,7 @@ _SIGNATURES = {
     "sw_set_spins": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_uint64]),
     "sw_get_labels": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
     "sw_threshold": (ctypes.c_uint32, [_P]),
+    "sw_label_passes": (ctypes.c_int32, [_P]),
     "sw_next_sweep": (ctypes.c_int64, [_P]),
     "sw_lattice": (ctypes.c_int32, [_P]),
     "sw_tile": (ctypes.c_int32, [_P]),
@@ -382,6 +383,11 @@ class Sim:
     @property
     def threshold(self) -> int:
         return sw_threshold(self.handle)
+
+    @property
+    def label_passes(self) -> int:
+        """Scan/analysis passes of the last sweep (label-equivalence sims)."""
+        return int(lib().sw_label_passes(self.handle))
 
     @property
     def next_sweep(self) -> int:

@@ -69,16 +69,21 @@ int validate(const sw_config *c) {
     if (c->init != SW_INIT_HOT && c->init != SW_INIT_COLD) return fail(SW_EINVAL, "init must be SW_INIT_HOT or SW_INIT_COLD");
     if (c->tile != 0 && c->tile != 32 && c->tile != 64) return fail(SW_EINVAL, "tile must be 0, 32 or 64");
     if (c->tile == 64 && c->L % 64 != 0) return fail(SW_EINVAL, "tile 64 needs L to be a multiple of 64");
-    if ((c->flags & ~(SW_FLAG_LABELS | SW_FLAG_DENSE_HIST)) != 0u) return fail(SW_EINVAL, "unknown flag bits");
+    if ((c->flags & ~(SW_FLAG_LABELS | SW_FLAG_DENSE_HIST | SW_FLAG_LABEL_EQUIV)) != 0u)
+        return fail(SW_EINVAL, "unknown flag bits");
     if (c->ring < 0 || c->ring > (int64_t)1 << 30) return fail(SW_EINVAL, "ring must be in [0, 2^30]");
     return SW_OK;
 }
 
 Layout layout_of(const sw_config &c) {
     const size_t L = (size_t)c.L, N = L * L;
+    const bool le = (c.flags & SW_FLAG_LABEL_EQUIV) != 0u;
     const size_t tw = (size_t)resolve_tile(c);
-    const size_t ntiles = (L / tw) * (L / tw);
-    const size_t ngroups = (ntiles + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
+    // the label-equivalence path keeps no tile structures; its group
+    // partials are one per kLeChunk sites
+    const size_t ntiles = le ? 0 : (L / tw) * (L / tw);
+    const size_t ngroups = le ? (N + swmi::kLeChunk - 1) / swmi::kLeChunk
+                              : (ntiles + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
     const size_t nodes = ntiles * swmi::kNodeSlots;
     const size_t ring = (size_t)(c.ring > 0 ? c.ring : kDefaultRing);
     Layout o{};
@@ -89,7 +94,7 @@ Layout layout_of(const sw_config &c) {
         return at;
     };
     o.spins[0] = take(N);
-    o.spins[1] = take(N);
+    o.spins[1] = le ? o.spins[0] : take(N);  // final spins in place
     o.parent[0] = take(nodes * 4);
     o.parent[1] = take(nodes * 4);
     o.nk[0] = take(ntiles * 4);
@@ -104,8 +109,12 @@ Layout layout_of(const sw_config &c) {
     o.acc = take(swmi::kAccWords * 8);
     o.tdev = take(8);
     o.ring = take(ring * sizeof(sw_obs));
-    o.labels = (c.flags & SW_FLAG_LABELS) ? take(N * 4) : 0;
+    o.labels = (le || (c.flags & SW_FLAG_LABELS)) ? take(N * 4) : 0;
     o.dense = (c.flags & SW_FLAG_DENSE_HIST) ? take((N + 1) * 8) : 0;
+    o.le_mask = le ? take(N) : 0;
+    o.le_cnt = le ? take(N * 4) : 0;
+    o.le_rsp = le ? take(N) : 0;
+    o.le_ctl = le ? take(64) : 0;
     o.total = off;
     return o;
 }
@@ -139,8 +148,17 @@ Dev make_dev(const sw_config &c, char *base, const Layout &lo) {
     d.acc = (uint64_t *)(base + lo.acc);
     d.tdev = (uint64_t *)(base + lo.tdev);
     d.ring = (sw_obs *)(base + lo.ring);
-    d.labels = (c.flags & SW_FLAG_LABELS) ? (uint32_t *)(base + lo.labels) : nullptr;
+    const bool le = (c.flags & SW_FLAG_LABEL_EQUIV) != 0u;
+    d.labels = (le || (c.flags & SW_FLAG_LABELS)) ? (uint32_t *)(base + lo.labels) : nullptr;
     d.dense = (c.flags & SW_FLAG_DENSE_HIST) ? (uint64_t *)(base + lo.dense) : nullptr;
+    if (le) {
+        d.ntiles = 0;
+        d.ngroups = (uint32_t)(((size_t)d.L * d.L + swmi::kLeChunk - 1) / swmi::kLeChunk);
+        d.le_mask = (uint8_t *)(base + lo.le_mask);
+        d.le_cnt = (uint32_t *)(base + lo.le_cnt);
+        d.le_rsp = (int8_t *)(base + lo.le_rsp);
+        d.le_ctl = (uint32_t *)(base + lo.le_ctl);
+    }
     return d;
 }
 
@@ -297,6 +315,13 @@ int sw_create_ex(const sw_config *cfg, void *dev_workspace, size_t ws_bytes, voi
     }
     const sw_config &c = s->cfg;
     s->dev = make_dev(c, (char *)s->ws, lo);
+    if (c.flags & SW_FLAG_LABEL_EQUIV) {
+        s->dev.le_grid = swmi::le_grid_size();
+        if (s->dev.le_grid == 0) {
+            sw_destroy(s);
+            return fail(SW_EHIP, "cannot size the cooperative labelling launch");
+        }
+    }
 
     // Everything starts at zero: no nodes in either parity, empty accumulators.
     e = hipMemsetAsync(s->ws, 0, lo.total, s->stream);
@@ -492,6 +517,15 @@ int sw_get_labels(sw_sim *s, uint32_t *host, int64_t n) {
     HIP_TRY(hipMemcpyAsync(host, s->dev.labels, (size_t)n * 4, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return SW_OK;
+}
+
+int32_t sw_label_passes(sw_sim *s) {
+    if (!s || !s->dev.le_ctl) return -1;
+    if (ensure_device(s) != SW_OK) return -1;
+    uint32_t v[2] = {0, 0};
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return -1;
+    if (hipMemcpy(v, s->dev.le_ctl + swmi::LE_PASSES, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    return v[1] ? -2 : (int32_t)v[0];
 }
 
 uint32_t sw_threshold(const sw_sim *s) { return s ? s->dev.T : 0u; }

@@ -58,9 +58,15 @@ struct Dev {
     sw_obs *ring;         // [ring_cap]
     uint32_t *labels;     // [N] or nullptr
     uint64_t *dense;      // [N + 1] or nullptr
+    // label-equivalence path (SW_FLAG_LABEL_EQUIV); nullptr otherwise
+    uint8_t *le_mask;     // [N] bonds of each site: bit 0 to E, bit 1 to N
+    uint32_t *le_cnt;     // [N] cluster size at each root
+    int8_t *le_rsp;       // [N] new spin, valid at roots
+    uint32_t *le_ctl;     // [8] pass flags (3), passes of the last sweep, status
     uint32_t L, tw, ntx, ntiles, ngroups;
     uint32_t T, seed_lo, seed_hi;
     uint32_t ring_cap;
+    uint32_t le_grid;     // workgroups of the cooperative labelling kernel (0: tile path)
     double J;
 };
 
@@ -89,6 +95,13 @@ struct BatchDev {
     const uint32_t *rmap;  // [n] the replicas (indices into devs) this launch covers
     uint32_t n, ntiles, nwmap, ngroups, nugroups, tw;
 };
+
+// Label-equivalence path: stages 0..4 of a sweep (bonds, iterated labelling,
+// new spins and sizes, statistics, record), and the cooperative grid size.
+hipError_t launch_le_stage(const Dev &d, int stage, hipStream_t s);
+uint32_t le_grid_size();
+constexpr uint32_t kLeChunk = 4096;  // sites per workgroup in the per-site passes
+enum { LE_PASSES = 3, LE_STATUS = 4 };
 
 hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s);
 hipError_t launch_batch_sweep(const BatchDev &b, hipStream_t s);

@@ -4,41 +4,12 @@
 // from bit arithmetic on ballot-sized masks, and only vertical bonds go
 // through the LDS union-find.
 #include "sw_internal.h"
+#include "sw_philox.h"
 
 namespace swmi {
 namespace {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
-// products; the key advances by the Weyl constants between rounds.
-__device__ __forceinline__ void philox10(uint32_t &x0, uint32_t &x1, uint32_t &x2,
-                                         uint32_t &x3, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t pa = (uint64_t)0xD2511F53u * x0;
-        const uint64_t pb = (uint64_t)0xCD9E8D57u * x2;
-        // three-input xor in one v_bitop3 (truth table 0x96)
-        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), x1, k0, 0x96);
-        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), x3, k1, 0x96);
-        x1 = (uint32_t)pb;
-        x3 = (uint32_t)pa;
-        x0 = n0;
-        x2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-// New spin (+1 / -1) of the cluster whose smallest site is r in sweep t:
-// bit r mod 128 of the 128-bit output for counter {r >> 7, t, 1, 0}.
-__device__ __forceinline__ int8_t cluster_spin(uint32_t r, uint32_t t, uint32_t k0, uint32_t k1) {
-    uint32_t w0 = r >> 7, w1 = t, w2 = 1u, w3 = 0u;
-    philox10(w0, w1, w2, w3, k0, k1);
-    const uint32_t q = (r >> 5) & 3u;
-    const uint32_t w = q == 0 ? w0 : q == 1 ? w1 : q == 2 ? w2 : w3;
-    return ((w >> (r & 31u)) & 1u) ? (int8_t)-1 : (int8_t)1;
-}
 
 template <int TW> struct RowOf;
 template <> struct RowOf<64> { using T = uint64_t; };
@@ -1069,7 +1040,7 @@ constexpr uint32_t kRecordTiles = 2048;  // tile partials per k_record workgroup
 __device__ __forceinline__ void record_fold(const Dev &d, uint32_t begin, uint32_t end, int mode, uint64_t *s_acc) {
     const uint32_t tid = threadIdx.x;
     unsigned long long *a = reinterpret_cast<unsigned long long *>(s_acc);
-    if (mode == 0) {
+    if (mode != 1) {
         const uint32_t f = tid & 63u, sub = tid >> 6;
         if (f < (uint32_t)GP_END) {
             uint64_t v = 0;
@@ -1101,13 +1072,16 @@ __device__ __forceinline__ void record_fold(const Dev &d, uint32_t begin, uint32
     }
 }
 
-// Writes the totals in s_acc: mode 0 the record of sweep t = *tdev (cluster
-// statistics) and t advances; both modes the energy and magnetisation of
-// the configuration sweep t-1 left, into record t-1.
+// Writes the totals in s_acc.  Mode 0 (end of a tile-pipeline sweep): the
+// record of sweep t = *tdev gets the cluster statistics and t advances; the
+// energy and magnetisation are those of the configuration sweep t-1 left
+// (measured by this sweep's tile kernel), written into record t-1.  Mode 1
+// (end of k_resolve): only that energy and magnetisation.  Mode 2 (end of a
+// label-equivalence sweep): every field of record t, and t advances.
 __device__ __forceinline__ void record_write(const Dev &d, const uint64_t *s_acc, int mode) {
     const uint32_t tid = threadIdx.x;
     const uint64_t tsw = *d.tdev;
-    if (mode == 0) {
+    if (mode != 1) {
         sw_obs *rec = &d.ring[tsw % d.ring_cap];
         if (tid == 0u) {
             rec->sweep = tsw;
@@ -1117,16 +1091,17 @@ __device__ __forceinline__ void record_write(const Dev &d, const uint64_t *s_acc
         }
         if (tid < 33u) rec->hist_log2[tid] = s_acc[GP_HIST + tid];
     }
-    if (tid == 0u && tsw >= 1u) {
-        sw_obs *prev = &d.ring[(tsw - 1u) % d.ring_cap];
+    const bool own = mode == 2;
+    if (tid == 0u && (own || tsw >= 1u)) {
+        sw_obs *rec = &d.ring[(own ? tsw : tsw - 1u) % d.ring_cap];
         const int64_t e = (int64_t)s_acc[GP_E];
-        prev->e_sum = e;
-        prev->energy = -d.J * (double)e;
-        prev->m_sum = (int64_t)s_acc[GP_M];
+        rec->e_sum = e;
+        rec->energy = -d.J * (double)e;
+        rec->m_sum = (int64_t)s_acc[GP_M];
     }
     __syncthreads();  // every thread has read the sweep index
     if (tid == 0u) {
-        if (mode == 0) *d.tdev = tsw + 1u;
+        if (mode != 1) *d.tdev = tsw + 1u;
         __threadfence();
     }
 }
@@ -1137,7 +1112,7 @@ __global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode
     const uint32_t tid = threadIdx.x;
     if (tid < (uint32_t)GP_END) s_acc[tid] = 0u;
     __syncthreads();
-    const uint32_t per = mode == 0 ? kRecordGroups : kRecordTiles;
+    const uint32_t per = mode != 1 ? kRecordGroups : kRecordTiles;
     const uint32_t begin = blockIdx.x * per;
     record_fold(d, begin, min(begin + per, nitems), mode, s_acc);
     __syncthreads();
@@ -1177,7 +1152,7 @@ __global__ __launch_bounds__(256) void k_record_b(const Dev *devs, const uint32_
     const uint32_t tid = threadIdx.x;
     if (tid < (uint32_t)GP_END) s_acc[tid] = 0u;
     __syncthreads();
-    record_fold(d, 0u, mode == 0 ? d.ngroups : d.ntiles, mode, s_acc);
+    record_fold(d, 0u, mode != 1 ? d.ngroups : d.ntiles, mode, s_acc);
     __syncthreads();
     record_write(d, s_acc, mode);
 }
@@ -1318,6 +1293,15 @@ hipError_t launch_init(const Dev &d, int cold, hipStream_t s) {
 
 hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
     const size_t n = (size_t)d.L * d.L;
+    if (d.le_grid) {  // label-equivalence path
+        if (stage == 0 && d.dense) k_zero_u64<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(d.dense, n + 1);
+        if (stage != 4) {
+            const hipError_t e = hipGetLastError();
+            return e != hipSuccess ? e : launch_le_stage(d, stage, s);
+        }
+        k_record<<<(d.ngroups + kRecordGroups - 1) / kRecordGroups, 256, 0, s>>>(d, d.ngroups, 2);
+        return hipGetLastError();
+    }
     switch (stage) {
     case 0:  // bonds + tile-local clusters
         if (d.dense) k_zero_u64<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(d.dense, n + 1);
@@ -1362,6 +1346,7 @@ hipError_t launch_sweep(const Dev &d, hipStream_t s) {
 }
 
 hipError_t launch_resolve(const Dev &d, hipStream_t s) {
+    if (d.le_grid) return hipSuccess;  // that path writes final spins and full records
     if (d.tw == 64)
         k_resolve<64><<<d.ntiles, 256, 0, s>>>(d);
     else

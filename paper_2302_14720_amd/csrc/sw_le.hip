@@ -1,0 +1,261 @@
+// sw_le.hip -- the paper's own cluster formation (Sec. 2.3): label
+// equivalence over the whole lattice in global memory, after Kalentev et
+// al.  Every site starts labelled with its own index; a scan pass lets each
+// site point the entry of its label at the smallest label among its bonded
+// neighbours (an atomic minimum), an analysis pass makes each site follow
+// its chain of references to the end and take that label, and the two
+// repeat until a scan changes nothing.  The result is the smallest site of
+// each cluster, the same canonical labels as the tile pipeline, so a sweep
+// gives the same bits.  The paper drove the passes from a dynamic-
+// parallelism kernel (Sec. 5); here one cooperative (persistent) kernel runs
+// all passes with grid-wide barriers and polls a device-side flag.  This
+// path exists to compare the paper's design with the tile pipeline.
+#include <hip/hip_cooperative_groups.h>
+
+#include "sw_internal.h"
+#include "sw_philox.h"
+
+namespace swmi {
+namespace {
+
+namespace cg = cooperative_groups;
+
+constexpr uint32_t kLeMaxPasses = 1u << 16;
+
+__device__ __forceinline__ uint32_t ld(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bonds (Sec. 2.1) of every site to E and N: two sites per Philox call,
+// words 2(s&1)+d of counter {s>>1, t, 0, 0}.
+__global__ __launch_bounds__(256) void k_le_bond(Dev d) {
+    const uint32_t L = d.L;
+    const size_t pairs = (size_t)L * L / 2u;
+    const uint32_t t = (uint32_t)*d.tdev;
+    const int8_t *sp = d.spins[0];
+    for (size_t p = blockIdx.x * (size_t)256 + threadIdx.x; p < pairs; p += (size_t)gridDim.x * 256) {
+        const size_t s0 = 2u * p;
+        const uint32_t y = (uint32_t)(s0 / L), x = (uint32_t)(s0 % L);
+        const size_t row = (size_t)y * L, up = (size_t)(y + 1u == L ? 0u : y + 1u) * L;
+        const int8_t a = sp[s0], b = sp[s0 + 1u];
+        const int8_t ea = b, eb = sp[row + (x + 2u == L ? 0u : x + 2u)];
+        const int8_t na = sp[up + x], nb = sp[up + x + 1u];
+        uint32_t w0 = (uint32_t)p, w1 = t, w2 = 0u, w3 = 0u;
+        philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
+        const uint32_t T = d.T;
+        const uint32_t m0 = (uint32_t)(a == ea && w0 < T) | ((uint32_t)(a == na && w1 < T) << 1);
+        const uint32_t m1 = (uint32_t)(b == eb && w2 < T) | ((uint32_t)(b == nb && w3 < T) << 1);
+        *reinterpret_cast<uint16_t *>(d.le_mask + s0) = (uint16_t)(m0 | (m1 << 8));
+    }
+}
+
+// All labelling passes in one cooperative launch.  Flags rotate over three
+// words: pass k raises flag k mod 3, every thread reads it after the pass's
+// last barrier, and flag (k+1) mod 3 is cleared at the start of pass k --
+// its last readers finished with pass k-2.  Every thread therefore takes
+// the same exit decision, and the pass cap bounds the loop.
+__global__ __launch_bounds__(256) void k_le_label(Dev d) {
+    cg::grid_group g = cg::this_grid();
+    const uint32_t L = d.L;
+    const size_t N = (size_t)L * L;
+    const size_t gid = blockIdx.x * (size_t)256 + threadIdx.x, stride = (size_t)gridDim.x * 256;
+    uint32_t *lab = d.labels;
+    const uint8_t *mk = d.le_mask;
+    uint32_t *ctl = d.le_ctl;
+    for (size_t i = gid; i < N; i += stride) st(&lab[i], (uint32_t)i);
+    if (gid == 0) {
+        st(&ctl[0], 0u);
+        st(&ctl[1], 0u);
+        st(&ctl[2], 0u);
+    }
+    g.sync();
+    uint32_t pass = 0;
+    while (true) {
+        const uint32_t f = pass % 3u;
+        if (gid == 0) st(&ctl[(pass + 1u) % 3u], 0u);
+        // scan: the entry of my label points at the smallest bonded label
+        bool changed = false;
+        for (size_t i = gid; i < N; i += stride) {
+            const uint32_t y = (uint32_t)(i / L), x = (uint32_t)(i % L);
+            const size_t row = (size_t)y * L;
+            const size_t e = row + (x + 1u == L ? 0u : x + 1u), w = row + (x == 0u ? L - 1u : x - 1u);
+            const size_t n = (size_t)(y + 1u == L ? 0u : y + 1u) * L + x;
+            const size_t s = (size_t)(y == 0u ? L - 1u : y - 1u) * L + x;
+            const uint32_t bm = mk[i], bw = mk[w], bs = mk[s];
+            const uint32_t l = ld(&lab[i]);
+            uint32_t m = l;
+            if (bm & 1u) m = min(m, ld(&lab[e]));
+            if (bm & 2u) m = min(m, ld(&lab[n]));
+            if (bw & 1u) m = min(m, ld(&lab[w]));
+            if (bs & 2u) m = min(m, ld(&lab[s]));
+            if (m < l) {
+                atomicMin(&lab[l], m);
+                changed = true;
+            }
+        }
+        if (changed) st(&ctl[f], 1u);
+        g.sync();
+        // analysis: follow the chain of references to its end
+        for (size_t i = gid; i < N; i += stride) {
+            const uint32_t l = ld(&lab[i]);
+            if (l == (uint32_t)i) continue;
+            uint32_t r = l, q = ld(&lab[r]);
+            while (q != r) {
+                r = q;
+                q = ld(&lab[r]);
+            }
+            if (r != l) st(&lab[i], r);
+        }
+        g.sync();
+        ++pass;
+        if (ld(&ctl[f]) == 0u || pass >= kLeMaxPasses) break;
+    }
+    if (gid == 0) {
+        st(&ctl[LE_PASSES], pass);
+        st(&ctl[LE_STATUS], ld(&ctl[(pass - 1u) % 3u]) != 0u ? 1u : 0u);
+    }
+}
+
+// New spin of every cluster (Sec. 2.4) at its root; sizes cleared.  A
+// wavefront's 64 sites lie in one 128-site block, so the Philox call of the
+// cluster-spin rule is the same for all its lanes.
+__global__ __launch_bounds__(256) void k_le_roots(Dev d) {
+    const size_t N = (size_t)d.L * d.L;
+    const uint32_t t = (uint32_t)*d.tdev;
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < N; i += (size_t)gridDim.x * 256) {
+        if (d.labels[i] != (uint32_t)i) continue;
+        d.le_rsp[i] = cluster_spin((uint32_t)i, t, d.seed_lo, d.seed_hi);
+        d.le_cnt[i] = 0u;
+    }
+}
+
+// Every site takes its cluster's spin; cluster sizes are counted per
+// workgroup in an LDS hash (kLeChunk sites each), then added to the roots.
+constexpr uint32_t kLeHash = 2048;
+__global__ __launch_bounds__(256) void k_le_flip(Dev d) {
+    __shared__ uint32_t hk[kLeHash];
+    __shared__ uint32_t hv[kLeHash];
+    for (uint32_t i = threadIdx.x; i < kLeHash; i += 256u) {
+        hk[i] = 0xFFFFFFFFu;
+        hv[i] = 0u;
+    }
+    __syncthreads();
+    const size_t N = (size_t)d.L * d.L;
+    const size_t b0 = (size_t)blockIdx.x * kLeChunk, b1 = min(b0 + kLeChunk, N);
+    int8_t *sp = d.spins[0];
+    for (size_t i = b0 + threadIdx.x; i < b1; i += 256u) {
+        const uint32_t r = d.labels[i];
+        sp[i] = d.le_rsp[r];
+        uint32_t h = (r * 2654435761u) >> 21;
+        bool placed = false;
+        for (int probe = 0; probe < 64 && !placed; ++probe) {
+            uint32_t cur = __hip_atomic_load(&hk[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (cur == 0xFFFFFFFFu) {
+                const uint32_t old = atomicCAS(&hk[h], 0xFFFFFFFFu, r);
+                cur = old == 0xFFFFFFFFu ? r : old;
+            }
+            if (cur == r) {
+                atomicAdd(&hv[h], 1u);
+                placed = true;
+            }
+            h = (h + 1u) & (kLeHash - 1u);
+        }
+        if (!placed) atomicAdd(&d.le_cnt[r], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kLeHash; i += 256u)
+        if (hk[i] != 0xFFFFFFFFu) atomicAdd(&d.le_cnt[hk[i]], hv[i]);
+}
+
+// Statistics of the new configuration and of the sweep's clusters, per
+// workgroup of kLeChunk sites, into the group partials (GP_* layout).
+__global__ __launch_bounds__(256) void k_le_stats(Dev d) {
+    __shared__ unsigned long long s_acc[GP_END];
+    for (uint32_t i = threadIdx.x; i < (uint32_t)GP_END; i += 256u) s_acc[i] = 0ull;
+    __syncthreads();
+    const uint32_t L = d.L;
+    const size_t N = (size_t)L * L;
+    const size_t b0 = (size_t)blockIdx.x * kLeChunk, b1 = min(b0 + kLeChunk, N);
+    const int8_t *sp = d.spins[0];
+    int64_t e = 0, m = 0;
+    uint64_t n = 0, mx = 0, sq = 0;
+    for (size_t i = b0 + threadIdx.x; i < b1; i += 256u) {
+        const uint32_t y = (uint32_t)(i / L), x = (uint32_t)(i % L);
+        const int32_t si = sp[i];
+        const int32_t se = sp[(size_t)y * L + (x + 1u == L ? 0u : x + 1u)];
+        const int32_t sn = sp[(size_t)(y + 1u == L ? 0u : y + 1u) * L + x];
+        e += si * se + si * sn;
+        m += si;
+        if (d.labels[i] == (uint32_t)i) {
+            const uint32_t S = d.le_cnt[i];
+            ++n;
+            mx = max(mx, (uint64_t)S);
+            sq += (uint64_t)S * S;
+            atomicAdd(&s_acc[GP_HIST + (31 - __clz((int)max(S, 1u)))], 1ull);
+            if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        e += __shfl_xor(e, o, 64);
+        m += __shfl_xor(m, o, 64);
+        n += __shfl_xor(n, o, 64);
+        mx = max(mx, (uint64_t)__shfl_xor((unsigned long long)mx, o, 64));
+        sq += __shfl_xor(sq, o, 64);
+    }
+    if ((threadIdx.x & 63u) == 0u) {
+        atomicAdd(&s_acc[GP_E], (unsigned long long)e);
+        atomicAdd(&s_acc[GP_M], (unsigned long long)m);
+        atomicAdd(&s_acc[GP_N], (unsigned long long)n);
+        atomicMax(&s_acc[GP_MAX], (unsigned long long)mx);
+        atomicAdd(&s_acc[GP_SQ], (unsigned long long)sq);
+    }
+    __syncthreads();
+    uint64_t *gp = d.gpart + (size_t)blockIdx.x * kGroupPart;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)GP_END; i += 256u) gp[i] = s_acc[i];
+}
+
+inline uint32_t grid_cap(size_t n, uint32_t per, uint32_t cap) {
+    size_t g = (n + per - 1) / per;
+    return (uint32_t)(g < 1 ? 1 : g > cap ? cap : g);
+}
+
+}  // namespace
+
+uint32_t le_grid_size() {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_le_label, 256, 0) != hipSuccess) return 0;
+    return (uint32_t)(cus * (per < 1 ? 1 : per));
+}
+
+hipError_t launch_le_stage(const Dev &d, int stage, hipStream_t s) {
+    const size_t N = (size_t)d.L * d.L;
+    switch (stage) {
+    case 0:
+        k_le_bond<<<grid_cap(N / 2, 256, 65536), 256, 0, s>>>(d);
+        break;
+    case 1: {
+        Dev dd = d;
+        void *args[] = {&dd};
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_le_label), dim3(d.le_grid), dim3(256),
+                                          args, 0, s);
+    }
+    case 2:
+        k_le_roots<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);
+        k_le_flip<<<(uint32_t)((N + kLeChunk - 1) / kLeChunk), 256, 0, s>>>(d);
+        break;
+    case 3:
+        k_le_stats<<<(uint32_t)((N + kLeChunk - 1) / kLeChunk), 256, 0, s>>>(d);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace swmi

@@ -755,23 +755,32 @@ __device__ __forceinline__ void ulocal_body(const Dev &d, const uint32_t ugroup)
     for (uint32_t i = tid; i < NG * kNodeSlots; i += 256u) s_p[i] = i;
     __syncthreads();
 
-    // tile-edges inside the group: E edges (lx < kUG-1), then N edges (ly < kUG-1)
+    // tile-edges inside the group: E edges (lx < kUG-1), then N edges (ly <
+    // kUG-1), one position per thread and iteration; all of a thread's loads
+    // are issued before its unions
     constexpr uint32_t NE = (kUG - 1u) * kUG;
-    for (uint32_t f = tid; f < 2u * NE * TW; f += 256u) {
-        const uint32_t e = f / TW, i = f % TW;
+    constexpr uint32_t NIT = 2u * NE * TW / 256u;
+    static_assert(2u * NE * TW % 256u == 0u, "edge positions must fill the workgroup");
+    uint32_t ua[NIT], ub[NIT];
+    bool uh[NIT];
+#pragma unroll
+    for (uint32_t it = 0; it < NIT; ++it) {
+        const uint32_t f = tid + 256u * it, e = f / TW, i = f % TW;
         const bool isn = e >= NE;
         const uint32_t e2 = isn ? e - NE : e;
         const uint32_t lx = isn ? e2 % kUG : e2 % (kUG - 1u), ly = isn ? e2 / kUG : e2 / (kUG - 1u);
         const uint32_t ta = ly * kUG + lx, tb = isn ? ta + kUG : ta + 1u;
-        bool has = valid(ta) && valid(tb);
-        uint32_t a = 0u, b = 0u;
-        if (has) {
-            const uint32_t A = tile_of(ta), B = tile_of(tb);
-            has = (d.xb[2u * A + (isn ? 1u : 0u)] >> i) & 1u;
-            const uint8_t *ea = d.edge + (size_t)A * 4u * TW, *eb = d.edge + (size_t)B * 4u * TW;
-            a = ta * kNodeSlots + (isn ? ea[3 * TW + i] : ea[1 * TW + i]);
-            b = tb * kNodeSlots + (isn ? eb[2 * TW + i] : eb[0 * TW + i]);
-        }
+        const bool ok = valid(ta) && valid(tb);
+        const uint32_t A = ok ? tile_of(ta) : 0u, B = ok ? tile_of(tb) : 0u;  // tile 0: read and ignored
+        const uint8_t *ea = d.edge + (size_t)A * 4u * TW, *eb = d.edge + (size_t)B * 4u * TW;
+        uh[it] = ok && ((d.xb[2u * A + (isn ? 1u : 0u)] >> i) & 1u);
+        ua[it] = ta * kNodeSlots + (isn ? ea[3 * TW + i] : ea[1 * TW + i]);
+        ub[it] = tb * kNodeSlots + (isn ? eb[2 * TW + i] : eb[0 * TW + i]);
+    }
+#pragma unroll
+    for (uint32_t it = 0; it < NIT; ++it) {
+        const uint32_t i = (tid + 256u * it) % TW, a = ua[it], b = ub[it];
+        const bool has = uh[it];
         // a run of bonds along the edge between the same two nodes needs one union
         const uint32_t pa = __shfl_up(a, 1, 64), pb = __shfl_up(b, 1, 64);
         const int ph = __shfl_up((int)has, 1, 64);
@@ -802,10 +811,20 @@ __global__ __launch_bounds__(256) void k_ulocal_b(const Dev *devs, const uint32_
 
 // One wavefront per (tile, direction): wave w of the launch takes tile w / 2
 // and its E (w even) or N (w odd) edge.
+// Plain lattices launch only the edges between kUG x kUG groups: wave w <
+// ngx * ntx takes the E edge of the last tile column of a group in tile row
+// w / ngx; the next ngx * ntx waves the N edges of the groups' last tile rows.
 template <int TW>
 __global__ __launch_bounds__(256) void k_union(Dev d) {
-    const uint32_t w = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (w / 2u < d.ntiles) union_body<TW>(d, w / 2u, w & 1u);
+    const uint32_t ntx = d.ntx, ngx = (ntx + kUG - 1u) / kUG, nE = ngx * ntx;
+    uint32_t w = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (w < nE) {
+        const uint32_t ty = w / ngx, tx = min((w % ngx) * kUG + kUG - 1u, ntx - 1u);
+        union_body<TW>(d, ty * ntx + tx, 0u);
+    } else if ((w -= nE) < nE) {
+        const uint32_t tx = w % ntx, ty = min((w / ntx) * kUG + kUG - 1u, ntx - 1u);
+        union_body<TW>(d, ty * ntx + tx, 1u);
+    }
 }
 
 template <int TW>
@@ -1311,13 +1330,13 @@ hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
             k_tile<32><<<d.ntiles, 64, 0, s>>>(d);
         break;
     case 1: {  // cross-tile unions: inside groups of tiles, then between groups
-        const uint32_t ngx = (d.ntx + kUG - 1u) / kUG;
+        const uint32_t ngx = (d.ntx + kUG - 1u) / kUG, nwaves = 2u * ngx * d.ntx;
         if (d.tw == 64) {
             k_ulocal<64><<<ngx * ngx, 256, 0, s>>>(d);
-            k_union<64><<<(d.ntiles + 1) / 2, 256, 0, s>>>(d);
+            k_union<64><<<(nwaves + 3u) / 4u, 256, 0, s>>>(d);
         } else {
             k_ulocal<32><<<ngx * ngx, 256, 0, s>>>(d);
-            k_union<32><<<(d.ntiles + 1) / 2, 256, 0, s>>>(d);
+            k_union<32><<<(nwaves + 3u) / 4u, 256, 0, s>>>(d);
         }
         break;
     }

@@ -50,9 +50,10 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def load_traffic(L: int):
-    """HBM bytes per k_tile launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+def load_counters(L: int):
+    """The committed rocprofv3 counter summary of k_tile (HBM bytes and
+    instruction counts per launch), if it was taken on the current kernel
+    source; else None."""
     p = os.path.join(ROOT, "profiles", f"k_tile_L{L}_counters.json")
     if not os.path.exists(p):
         return None
@@ -60,7 +61,11 @@ def load_traffic(L: int):
         d = json.load(f)
     if d.get("kernel_source_sha256") != kernel_source_sha():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
+
+
+# VALU issue ceiling: one wave64 instruction per SIMD every 4 cycles
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def cpu_baseline(L: int, seed: int):
@@ -312,7 +317,9 @@ def main() -> int:
         alu_ach = alu_ops / t_dom / 1e12
         hbm_frac = hbm_ach / HBM_PEAK_GBS
         alu_frac = alu_ach / ALU_PEAK_TOPS
-        traffic = load_traffic(L)
+        cnt = load_counters(L)
+        traffic = cnt.get("hbm_bytes_per_launch") if cnt else None
+        valu = cnt.get("valu_wave_instructions_per_launch") if cnt else None
         if alu_frac >= hbm_frac:
             roofline = {"bound": "alu", "achieved": alu_ach, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
                         "frac": alu_frac, "traffic": traffic}
@@ -321,7 +328,10 @@ def main() -> int:
                         "frac": hbm_frac, "traffic": traffic}
         roofline.update({"kernel": "k_tile", "kernel_ms": per_sweep[dom],
                          "hbm_achieved_GBs": hbm_ach, "hbm_frac": hbm_frac,
-                         "alu_achieved_Tops": alu_ach, "alu_frac": alu_frac})
+                         "alu_achieved_Tops": alu_ach, "alu_frac": alu_frac,
+                         # issued VALU wave instructions (all work, not only the
+                         # algorithmic Philox ops) against the issue ceiling
+                         "valu_issue_frac": (valu / t_dom / VALU_ISSUE_PEAK) if valu else None})
     else:
         roofline = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
                     "traffic": None, "kernel": dom, "kernel_ms": per_sweep[dom]}

@@ -1,0 +1,114 @@
+"""Parity at the full sizes and sweep counts of the benchmark workloads.
+
+The oracle cannot run them end to end in test time, but every random draw
+is keyed by (seed, sweep, site), so it can restart from any state the GPU
+reaches: each test runs the GPU chain to its full length, checkpoints the
+spins, and compares the following sweeps with the oracle bit for bit, plus
+the record invariants over every sweep of the run."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2302_14720_amd as sw
+from paper_2302_14720_amd.replicas import grid_table
+
+pytestmark = pytest.mark.gpu
+
+BETA_C = math.log(1.0 + math.sqrt(2.0)) / 2.0
+FIELDS = ("sweep", "e_sum", "energy", "m_sum", "n_clusters", "max_cluster", "sum_sq_sizes")
+
+
+def _same_records(a, b, where):
+    assert len(a) == len(b), where
+    for f in FIELDS:
+        bad = np.nonzero(a[f] != b[f])[0]
+        assert bad.size == 0, f"{where} field {f}: first mismatch at record {bad[0]}"
+    assert np.array_equal(a["hist_log2"], b["hist_log2"]), f"{where} hist_log2"
+
+
+def _invariants(recs, N, where):
+    assert np.all((recs["e_sum"] - 2 * N) % 4 == 0), where
+    assert np.all(np.abs(recs["e_sum"]) <= 2 * N), where
+    assert np.all((recs["m_sum"] - N) % 2 == 0), where
+    assert np.all(recs["hist_log2"].sum(axis=1) == recs["n_clusters"]), where
+    assert np.all(recs["max_cluster"] <= N) and np.all(recs["n_clusters"] >= 1), where
+    # sum of sizes^2 lies between N^2 / n_clusters (Cauchy-Schwarz) and N * max
+    sq = recs["sum_sq_sizes"].astype(np.float64)
+    assert np.all(sq <= float(N) * recs["max_cluster"].astype(np.float64)), where
+    assert np.all(sq * recs["n_clusters"].astype(np.float64) >= float(N) * float(N) * (1 - 1e-12)), where
+
+
+@pytest.mark.parametrize("beta,seed", [(0.30, 10), (BETA_C, 11), (0.60, 12)])
+def test_L1024_2000_sweeps(beta, seed):
+    L, n, tail = 1024, 2000, 8
+    print(f"\n[case] L=1024 beta={beta} seed={seed}: {n} sweeps", flush=True)
+    with sw.Sim(L, beta, 1.0, seed) as s:
+        s.sweep(n - tail)
+        state = s.spins()
+        s.sweep(tail)
+        recs = s.series(0, n)
+        final = s.spins()
+    _invariants(recs, L * L, f"beta={beta}")
+    ref = oracle.run(L, 1.0, oracle.threshold(beta, 1.0), seed, n - tail, tail, state)
+    _same_records(recs[n - tail:], ref, f"L=1024 beta={beta} sweeps {n - tail}..{n - 1}")
+    assert np.array_equal(final, state)
+
+
+@pytest.mark.parametrize("cold", [False, True])
+def test_L16384_benchmark_chain(cold):
+    """The benchmark's lattice and launch configuration (torch workspace and
+    stream, graph-replayed sweeps): 200 sweeps, then the last one against
+    one oracle sweep from the GPU's own state; a cold start also checks its
+    first sweep (one near-spanning cluster) against the oracle."""
+    L, seed, n = 16384, 3 if cold else 4, 200
+    N = L * L
+    T = oracle.threshold(BETA_C, 1.0)
+    print(f"\n[case] L=16384 {'cold' if cold else 'hot'} start seed={seed}: {n} sweeps", flush=True)
+    with sw.Sim(L, BETA_C, 1.0, seed, init=sw.SW_INIT_COLD if cold else sw.SW_INIT_HOT) as s:
+        assert s.threshold == T
+        if cold:
+            s.sweep(1)
+            first = s.spins()
+            rec0 = s.series(0, 1)[0]
+            s.sweep(19)
+        else:
+            s.sweep(20)
+        s.sweep(n - 21)
+        state = s.spins()
+        s.sweep(1)
+        recs = s.series(0, n)
+        final = s.spins()
+    _invariants(recs, N, "L=16384")
+    last, _, _ = oracle.sweep(L, 1.0, T, seed, n - 1, state)
+    assert last.tobytes() == recs[n - 1].tobytes()
+    assert np.array_equal(final, state)
+    del state, final
+    if cold:
+        sp = oracle.init(L, seed, cold=True)
+        r0, _, _ = oracle.sweep(L, 1.0, T, seed, 0, sp)
+        assert r0.tobytes() == rec0.tobytes()
+        assert np.array_equal(first, sp)
+
+
+def test_grid_batch_5000_sweeps():
+    """The 256-replica grid for its full 5000 sweeps as one batch; one
+    replica of each side against a plain sim run alone (last 64 records and
+    final spins), every replica against the record invariants."""
+    L, beta, seed = grid_table()
+    n, ring = 5000, 64
+    print(f"\n[case] batch grid 256 replicas: {n} sweeps", flush=True)
+    with sw.Batch(L, beta, 1.0, seed, ring=ring) as b:
+        b.sweep(n)
+        recs = [b.series(r, n - ring, ring) for r in range(len(L))]
+        picks = (5, 11, 17, 23, 254)  # L = 64, 128, 256, 512, 1024
+        spins = {r: b.spins(r) for r in picks}
+    for r in range(len(L)):
+        _invariants(recs[r], int(L[r]) ** 2, f"replica {r}")
+        assert int(recs[r]["sweep"][-1]) == n - 1
+    for r in picks:
+        with sw.Sim(int(L[r]), float(beta[r]), 1.0, int(seed[r]), ring=ring) as s:
+            s.sweep(n)
+            _same_records(recs[r], s.series(n - ring, ring), f"replica {r}")
+            assert np.array_equal(spins[r], s.spins())

@@ -95,10 +95,14 @@ def batched_vs_plain(args):
     import paper_2302_14720_amd as sw
     from paper_2302_14720_amd.replicas import grid_table
 
+    from paper_2302_14720_amd import autotune
+
     L, beta, seed = grid_table(256, 1000)
     sites = int((L.astype("int64") ** 2).sum())
-    print(f"[bench] batched: {len(L)} replicas, {sites} sites", file=sys.stderr, flush=True)
-    b = sw.Batch(L, beta, 1.0, seed)
+    tile, tune_ms = autotune.tune_batch(L, beta, 1.0, seed, sweeps=10, use_cache=False)
+    print(f"[bench] batched: {len(L)} replicas, {sites} sites; autotuned tile {tile} ({tune_ms} ms/sweep)",
+          file=sys.stderr, flush=True)
+    b = sw.Batch(L, beta, 1.0, seed, tile=tile)
     b.sweep(args.warmup)
     b.sync()
     t0 = time.perf_counter()
@@ -131,7 +135,8 @@ def batched_vs_plain(args):
     return {
         "workload": "256 replicas, L = {64,128,256,512,1024}[r mod 5], beta_k = 0.40 + 0.08 k/31 "
                     "(k = r // 8), seed 1000 + r, hot start, J = 1",
-        "replicas": len(L), "sites": sites,
+        "replicas": len(L), "sites": sites, "tile": tile,
+        "autotune_ms_per_sweep": {str(k): v for k, v in tune_ms.items()},
         "value": bval, "unit": "site-updates/s", "sweeps": args.batch_steps,
         "ms_per_step": bdt * 1e3 / args.batch_steps,
         "plain_value": pval, "plain_sweeps": args.plain_steps,

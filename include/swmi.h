@@ -215,21 +215,25 @@ const char *sw_last_error(void);
  * every L[r] is a multiple of 64, else 32); no labels or dense histogram. */
 typedef struct sw_batch sw_batch;
 
-/* Device bytes of a batch with these lattice sides and `ring` records per
- * replica (0 = 1024); 0 when the arguments are invalid. */
-size_t sw_batch_workspace_bytes(int32_t n, const int32_t *L, int64_t ring);
+/* Device bytes of a batch with these lattice sides, `ring` records per
+ * replica (0 = 1024) and tile side (0 = automatic, 32, 64); 0 when the
+ * arguments are invalid. */
+size_t sw_batch_workspace_bytes(int32_t n, const int32_t *L, int64_t ring, int32_t tile);
 
 /* Creates a batch of n replicas, L/beta/J/seed being arrays of length n
  * (host memory, read during the call), all started with `init`
- * (SW_INIT_HOT / SW_INIT_COLD), t = 0.  dev_workspace: NULL (the library
+ * (SW_INIT_HOT / SW_INIT_COLD), t = 0.  tile: the side of the tiles every
+ * replica is labelled in -- 0 (64 when every L is a multiple of 64, else
+ * 32), 32 or 64 (results do not depend on it; the binding's autotuner picks
+ * the faster one for a given replica table).  dev_workspace: NULL (the library
  * allocates) or a 256-byte-aligned device buffer of >= ws_bytes =
  * sw_batch_workspace_bytes(...) bytes that the caller keeps alive until
  * sw_batch_destroy.  hip_stream: the stream for all of the batch's work
  * (NULL with dev_workspace NULL: the library creates one).  SW_EINVAL for a
  * bad replica (the message names it), SW_ENOMEM for a small workspace. */
 int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const double *J,
-                    const uint64_t *seed, int32_t init, int64_t ring, void *dev_workspace,
-                    size_t ws_bytes, void *hip_stream, sw_batch **out);
+                    const uint64_t *seed, int32_t init, int64_t ring, int32_t tile,
+                    void *dev_workspace, size_t ws_bytes, void *hip_stream, sw_batch **out);
 
 /* Re-initialises every replica (SW_INIT_HOT / SW_INIT_COLD) and sets t = 0. */
 int sw_batch_reset(sw_batch *batch, int32_t init_mode);

@@ -98,9 +98,9 @@ _SIGNATURES = {
     "sw_tile": (ctypes.c_int32, [_P]),
     "sw_destroy": (None, [_P]),
     "sw_last_error": (ctypes.c_char_p, []),
-    "sw_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, _P, ctypes.c_int64]),
+    "sw_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32]),
     "sw_batch_create": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64,
-                                       _P, ctypes.c_size_t, _P, _P]),
+                                       ctypes.c_int32, _P, ctypes.c_size_t, _P, _P]),
     "sw_batch_reset": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sw_batch_sweep": (ctypes.c_int, [_P, ctypes.c_int64]),
     "sw_batch_sync": (ctypes.c_int, [_P]),
@@ -274,16 +274,16 @@ def _replica_arrays(L, beta, J, seed):
     return n, La, ba, Ja, sa
 
 
-def sw_batch_workspace_bytes(L, ring: int = 0) -> int:
+def sw_batch_workspace_bytes(L, ring: int = 0, tile: int = 0) -> int:
     La = np.ascontiguousarray(L, dtype=np.int32)
-    return int(lib().sw_batch_workspace_bytes(La.size, _ptr(La), ring))
+    return int(lib().sw_batch_workspace_bytes(La.size, _ptr(La), ring, tile))
 
 
-def sw_batch_create(L, beta, J, seed, init: int = SW_INIT_HOT, ring: int = 0, ws_ptr: int = 0,
+def sw_batch_create(L, beta, J, seed, init: int = SW_INIT_HOT, ring: int = 0, tile: int = 0, ws_ptr: int = 0,
                     ws_bytes: int = 0, stream_ptr: int = 0) -> int:
     n, La, ba, Ja, sa = _replica_arrays(L, beta, J, seed)
     h = ctypes.c_void_p()
-    _check(lib().sw_batch_create(n, _ptr(La), _ptr(ba), _ptr(Ja), _ptr(sa), init, ring, ws_ptr or None,
+    _check(lib().sw_batch_create(n, _ptr(La), _ptr(ba), _ptr(Ja), _ptr(sa), init, ring, tile, ws_ptr or None,
                                  ws_bytes, stream_ptr or None, ctypes.byref(h)))
     return h.value
 
@@ -421,21 +421,22 @@ class Batch:
     sequence of lattice sides; beta, J and seed are scalars or sequences of
     the same length."""
 
-    def __init__(self, L, beta, J=1.0, seed=0, *, init: int = SW_INIT_HOT, ring: int = 0, device=None):
+    def __init__(self, L, beta, J=1.0, seed=0, *, init: int = SW_INIT_HOT, ring: int = 0, tile: int = 0,
+                 device=None):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("Batch needs a ROCm GPU (torch.cuda.is_available() is False)")
         n, La, ba, Ja, sa = _replica_arrays(L, beta, J, seed)
         self.L = La.tolist()
-        nbytes = sw_batch_workspace_bytes(La, ring)
+        nbytes = sw_batch_workspace_bytes(La, ring, tile)
         if nbytes == 0:
-            self.handle = sw_batch_create(La, ba, Ja, sa, init, ring)  # raises with the reason
+            self.handle = sw_batch_create(La, ba, Ja, sa, init, ring, tile)  # raises with the reason
         dev = torch.device("cuda" if device is None else device)
         self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self._stream = torch.cuda.Stream(device=dev)
         torch.cuda.current_stream(dev).synchronize()
-        self.handle = sw_batch_create(La, ba, Ja, sa, init, ring, self._ws.data_ptr(), nbytes,
+        self.handle = sw_batch_create(La, ba, Ja, sa, init, ring, tile, self._ws.data_ptr(), nbytes,
                                       self._stream.cuda_stream)
 
     def __len__(self) -> int:

@@ -578,14 +578,16 @@ struct BatchPlan {
 // Validates the replica table and lays out the batch workspace: the
 // replicas' buffers one after another, then the Dev table and the maps.
 int plan_batch(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
-               int32_t init, int64_t ring, BatchPlan *p) {
+               int32_t init, int64_t ring, int32_t tile, BatchPlan *p) {
     if (n < 1 || n > swmi::kMaxReplicas)
         return fail(SW_EINVAL, "the number of replicas must be in [1, " + std::to_string(swmi::kMaxReplicas) + "]");
     if (!L || !beta || !J || !seed) return fail(SW_EINVAL, "replica arrays must not be NULL");
     if (init != SW_INIT_HOT && init != SW_INIT_COLD) return fail(SW_EINVAL, "init must be SW_INIT_HOT or SW_INIT_COLD");
+    if (tile != 0 && tile != 32 && tile != 64) return fail(SW_EINVAL, "tile must be 0, 32 or 64");
     bool all64 = true;
     for (int32_t r = 0; r < n; ++r) all64 = all64 && (L[r] % 64 == 0);
-    p->tw = all64 ? 64u : 32u;
+    if (tile == 64 && !all64) return fail(SW_EINVAL, "tile 64 needs every L to be a multiple of 64");
+    p->tw = tile != 0 ? (uint32_t)tile : all64 ? 64u : 32u;
     p->cfg.assign((size_t)n, sw_config{});
     p->base.assign((size_t)n, 0);
     size_t off = 0;
@@ -676,22 +678,22 @@ int batch_check_replica(const sw_batch *b, int32_t r) {
 
 extern "C" {
 
-size_t sw_batch_workspace_bytes(int32_t n, const int32_t *L, int64_t ring) {
+size_t sw_batch_workspace_bytes(int32_t n, const int32_t *L, int64_t ring, int32_t tile) {
     if (n < 1 || n > swmi::kMaxReplicas || !L) return 0;
     std::vector<double> beta((size_t)n, 0.0), J((size_t)n, 1.0);
     std::vector<uint64_t> seed((size_t)n, 0u);
     BatchPlan p;
-    if (plan_batch(n, L, beta.data(), J.data(), seed.data(), SW_INIT_HOT, ring, &p) != SW_OK) return 0;
+    if (plan_batch(n, L, beta.data(), J.data(), seed.data(), SW_INIT_HOT, ring, tile, &p) != SW_OK) return 0;
     return p.total;
 }
 
 int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
-                    int32_t init, int64_t ring, void *dev_workspace, size_t ws_bytes, void *hip_stream,
-                    sw_batch **out) {
+                    int32_t init, int64_t ring, int32_t tile, void *dev_workspace, size_t ws_bytes,
+                    void *hip_stream, sw_batch **out) {
     if (!out) return fail(SW_EINVAL, "out is NULL");
     *out = nullptr;
     BatchPlan p;
-    int rc = plan_batch(n, L, beta, J, seed, init, ring, &p);
+    int rc = plan_batch(n, L, beta, J, seed, init, ring, tile, &p);
     if (rc != SW_OK) return rc;
     if (dev_workspace && ws_bytes < p.total)
         return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes");

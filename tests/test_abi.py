@@ -80,6 +80,9 @@ def test_batch_workspace_sizes_and_validation():
     n1 = sw.sw_batch_workspace_bytes(L)
     assert n1 > sum(sw.sw_workspace_bytes(int(x)) // 4 for x in L)
     assert sw.sw_batch_workspace_bytes(L, ring=4096) > n1
+    assert sw.sw_batch_workspace_bytes(L, tile=32) > n1  # more, smaller tiles
+    assert sw.sw_batch_workspace_bytes(np.array([64, 96], dtype=np.int32), tile=64) == 0
+    assert sw.sw_batch_workspace_bytes(L, tile=48) == 0
     assert sw.sw_batch_workspace_bytes(np.array([64, 100], dtype=np.int32)) == 0
     assert sw.sw_batch_workspace_bytes(np.zeros(0, dtype=np.int32)) == 0
     assert sw.sw_batch_workspace_bytes(np.full(4097, 64, dtype=np.int32)) == 0
@@ -89,10 +92,10 @@ def test_batch_workspace_sizes_and_validation():
     s = np.array([1, 2], dtype=np.uint64)
     bad_L = np.array([64, 33], dtype=np.int32)
     rc = lib.sw_batch_create(2, bad_L.ctypes.data_as(ctypes.c_void_p), b[0].ctypes.data_as(ctypes.c_void_p),
-                             b[1].ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p), 0, 0,
+                             b[1].ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p), 0, 0, 0,
                              None, 0, None, ctypes.byref(h))
     assert rc == sw.SW_EINVAL and b"replica 1" in lib.sw_last_error()
-    rc = lib.sw_batch_create(0, None, None, None, None, 0, 0, None, 0, None, ctypes.byref(h))
+    rc = lib.sw_batch_create(0, None, None, None, None, 0, 0, 0, None, 0, None, ctypes.byref(h))
     assert rc == sw.SW_EINVAL
     assert lib.sw_batch_size(None) == 0 and lib.sw_batch_next_sweep(None) == -1
 

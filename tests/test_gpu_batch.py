@@ -127,3 +127,25 @@ def test_batch_errors():
         with pytest.raises(sw.SwError) as e:
             b.series(0, 0, 2)
         assert e.value.code == sw.SW_ERANGE
+
+
+def test_autotuner_picks_an_allowed_tile(tmp_path, monkeypatch):
+    from paper_2302_14720_amd import autotune
+
+    monkeypatch.setenv("SWMI_TUNE_CACHE", str(tmp_path / "tune.json"))
+    L = [64, 128, 256]
+    tile, ms = autotune.tune_batch(L, [0.41, 0.44, 0.47], 1.0, [1, 2, 3], sweeps=4, warmup=1)
+    assert tile in (32, 64) and set(ms) == {32, 64} and all(v > 0 for v in ms.values())
+    assert ms[tile] == min(ms.values())
+    again, _ = autotune.tune_batch(L, [0.41, 0.44, 0.47], 1.0, [1, 2, 3])
+    assert again == tile  # served from the cache
+    t2, ms2 = autotune.tune_sim(96, 0.44, sweeps=3, warmup=1)
+    assert t2 == 32 and set(ms2) == {32}
+    # the tuned tile changes no bit
+    with _batch(L, [0.41, 0.44, 0.47], [1, 2, 3], tile=tile) as b1, \
+            _batch(L, [0.41, 0.44, 0.47], [1, 2, 3], tile=96 - tile) as b2:
+        b1.sweep(6)
+        b2.sweep(6)
+        for r in range(3):
+            _same_records(b1.series(r, 0, 6), b2.series(r, 0, 6), f"replica {r}")
+            assert np.array_equal(b1.spins(r), b2.spins(r))

@@ -25,19 +25,6 @@ __device__ __forceinline__ uint32_t hsb_le(uint32_t B, uint32_t x) {
     return 31u - (uint32_t)__clz((int)m);
 }
 
-// Length of the run that starts at x (B: run-start mask of the row, bit x set).
-template <typename Row>
-__device__ __forceinline__ uint32_t run_len_row(Row B, uint32_t x) {
-    constexpr uint32_t W = sizeof(Row) * 8;
-    const Row above = x + 1u < W ? (Row)(B & (Row)(~(Row)0 << (x + 1u))) : (Row)0;
-    uint32_t next;
-    if constexpr (sizeof(Row) == 8)
-        next = above ? (uint32_t)__ffsll((long long)above) - 1u : W;
-    else
-        next = above ? (uint32_t)__ffs((int)above) - 1u : W;
-    return next - x;
-}
-
 // Workgroup b runs on XCD b % 8; give each XCD a contiguous band of tiles so
 // that neighbouring tiles (which share halo rows and cache lines) meet in
 // the same L2.
@@ -63,30 +50,6 @@ __device__ __forceinline__ uint32_t lds_find(uint32_t *par, uint32_t a) {
         if (gp == p) return p;
         atomicMin(&par[a], gp);
         a = gp;
-    }
-}
-// Union of the sets of a and b.  Both finds advance together, so their LDS
-// loads overlap; the larger root is then linked under the smaller one by
-// compare-and-swap, retrying if another lane linked it first.  No path
-// compression here: the pass after the unions points every run start at its
-// root.
-__device__ __forceinline__ void lds_union2(uint32_t *par, uint32_t a, uint32_t b) {
-    while (true) {
-        uint32_t pa = lds_load(&par[a]), pb = lds_load(&par[b]);
-        while (pa != a || pb != b) {
-            a = pa;
-            b = pb;
-            pa = lds_load(&par[a]);
-            pb = lds_load(&par[b]);
-        }
-        if (a == b) return;
-        const uint32_t hi = max(a, b), lo = min(a, b);
-        uint32_t expected = hi;
-        if (__hip_atomic_compare_exchange_strong(&par[hi], &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
-            return;
-        a = lo;
-        b = expected;
     }
 }
 // The tile kernel's parent words hold byte offsets into the LDS array (so a
@@ -167,26 +130,6 @@ __device__ __forceinline__ uint32_t g_load(uint32_t *p) {
 }
 __device__ __forceinline__ void g_store(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t g_find(uint32_t *par, uint32_t a) {
-    while (true) {
-        const uint32_t p = g_load(&par[a]);
-        if (p == a) return a;
-        const uint32_t gp = g_load(&par[p]);
-        if (gp == p) return p;
-        g_store(&par[a], gp);
-        a = gp;
-    }
-}
-// Root of a without writing anything: used once the unions are complete, so
-// that every store that follows is a root (a halving store racing with them
-// could leave a non-root ancestor behind).
-__device__ __forceinline__ uint32_t g_root(const uint32_t *par, uint32_t a) {
-    while (true) {
-        const uint32_t p = __hip_atomic_load(&par[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (p == a) return a;
-        a = p;
-    }
 }
 // Both finds advance together (their loads overlap), each with path
 // halving: a node is re-pointed at its grandparent, which is an ancestor

@@ -196,17 +196,23 @@ int admit(sw_server *s) {
         Job *j = s->queue.front();
         size_t off = 0;
         if (!s->pool.alloc(j->bytes, &off)) break;
-        s->queue.pop_front();
-        j->off = off;
-        j->slot = s->free_slots.back();
-        s->free_slots.pop_back();
+        const int32_t slot = s->free_slots.back();
         char *base = (char *)s->pool_mem + off;
-        j->dev = swmi::make_dev(j->cfg, base, swmi::layout_of(j->cfg));
-        HIP_TRY(hipStreamSynchronize(s->stream));
-        HIP_TRY(hipMemsetAsync(base, 0, j->bytes, s->stream));
-        HIP_TRY(swmi::launch_init(j->dev, j->cfg.init == SW_INIT_COLD ? 1 : 0, s->stream));
-        HIP_TRY(hipStreamSynchronize(s->stream));
-        HIP_TRY(hipMemcpy(s->d_devs + j->slot, &j->dev, sizeof(Dev), hipMemcpyHostToDevice));
+        const Dev dev = swmi::make_dev(j->cfg, base, swmi::layout_of(j->cfg));
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(base, 0, j->bytes, s->stream);
+        if (e == hipSuccess) e = swmi::launch_init(dev, j->cfg.init == SW_INIT_COLD ? 1 : 0, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e == hipSuccess) e = hipMemcpy(s->d_devs + slot, &dev, sizeof(Dev), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {  // the job stays queued; its memory and slot are returned
+            s->pool.release(off, j->bytes);
+            return swmi::hip_fail(e, "admitting a job");
+        }
+        s->queue.pop_front();
+        s->free_slots.pop_back();
+        j->off = off;
+        j->slot = slot;
+        j->dev = dev;
         j->state = SW_JOB_ACTIVE;
         s->active.push_back(j);
         s->dirty = true;

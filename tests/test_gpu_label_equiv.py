@@ -25,7 +25,8 @@ def _same_records(a, b, where):
 
 def _le(L, beta, seed, **kw):
     print(f"\n[case] label-equivalence L={L} beta={beta} seed={seed} {kw}", flush=True)
-    return sw.Sim(L, beta, 1.0, seed, flags=sw.SW_FLAG_LABEL_EQUIV, **kw)
+    kw.setdefault("flags", sw.SW_FLAG_LABEL_EQUIV)
+    return sw.Sim(L, beta, 1.0, seed, **kw)
 
 
 @pytest.mark.parametrize("L", [32, 64, 96, 128])
@@ -73,3 +74,14 @@ def test_matches_tile_pipeline(L, beta, cold):
         passes = s.label_passes
         print(f"[info] L={L} beta={beta:.4f}: {passes} label-equivalence passes in the last sweep", flush=True)
         assert 1 <= passes < 1000
+
+
+def test_dense_histogram():
+    L, seed, n, beta = 96, 21, 6, BETA_C
+    sp = oracle.init(L, seed)
+    T = oracle.threshold(beta, 1.0)
+    oracle.run(L, 1.0, T, seed, 0, n - 1, sp)
+    _, _, _, dense = oracle.sweep(L, 1.0, T, seed, n - 1, sp, dense=True)
+    with _le(L, beta, seed, flags=sw.SW_FLAG_LABEL_EQUIV | sw.SW_FLAG_DENSE_HIST) as s:
+        s.sweep(n)
+        assert np.array_equal(s.cluster_hist(), dense)

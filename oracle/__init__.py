@@ -76,6 +76,18 @@ def _bind(l: ctypes.CDLL) -> ctypes.CDLL:
     l.orc_chains.restype = ctypes.c_int
     l.orc_one_step_codes.argtypes = [i32, u32, u64, i64, u32, P, P]
     l.orc_one_step_codes.restype = ctypes.c_int
+    l.orc_potts_threshold.argtypes = [f64, f64]
+    l.orc_potts_threshold.restype = u32
+    l.orc_potts_init.argtypes = [i32, u64, i32, i32, P]
+    l.orc_potts_init.restype = None
+    l.orc_potts_spin.argtypes = [u64, u32, u32, i32]
+    l.orc_potts_spin.restype = i32
+    l.orc_potts_sweep.argtypes = [i32, f64, u32, i32, u64, u32, P, P, P]
+    l.orc_potts_sweep.restype = ctypes.c_int
+    l.orc_potts_run.argtypes = [i32, f64, u32, i32, u64, u32, i64, P, P]
+    l.orc_potts_run.restype = ctypes.c_int
+    l.orc_potts_chains.argtypes = [i32, f64, u32, i32, u64, i64, i32, P, P]
+    l.orc_potts_chains.restype = ctypes.c_int
     return l
 
 
@@ -220,3 +232,45 @@ def one_step_codes(L: int, T: int, seed0: int, nseeds: int, t: int,
     if rc != 0:
         raise ValueError("oracle one_step_codes: lattice too large")
     return codes
+
+
+# ------------------------------------------------------------ q-state Potts
+def potts_threshold(beta: float, J: float = 1.0) -> int:
+    return int(lib().orc_potts_threshold(beta, J))
+
+
+def potts_init(L: int, seed: int, q: int, cold: bool = False) -> np.ndarray:
+    s = np.empty(L * L, dtype=np.int8)
+    lib().orc_potts_init(L, seed, q, 1 if cold else 0, _p(s))
+    return s
+
+
+def potts_spin(seed: int, t: int, root: int, q: int) -> int:
+    return int(lib().orc_potts_spin(seed, t, root, q))
+
+
+def potts_sweep(L: int, J: float, T: int, q: int, seed: int, t: int, spins: np.ndarray):
+    """One Potts sweep in place on ``spins``; returns (record, labels)."""
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous and spins.size == L * L
+    lab = np.empty(L * L, dtype=np.uint32)
+    rec = np.zeros(1, dtype=OBS_DTYPE)
+    if lib().orc_potts_sweep(L, J, T, q, seed, t, _p(spins), _p(lab), _p(rec)) != 0:
+        raise MemoryError("oracle potts sweep: allocation failed")
+    return rec[0], lab
+
+
+def potts_run(L: int, J: float, T: int, q: int, seed: int, t0: int, count: int,
+              spins: np.ndarray) -> np.ndarray:
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous and spins.size == L * L
+    recs = np.zeros(count, dtype=OBS_DTYPE)
+    if lib().orc_potts_run(L, J, T, q, seed, t0, count, _p(spins), _p(recs)) != 0:
+        raise MemoryError("oracle potts run: allocation failed")
+    return recs
+
+
+def potts_chains(L: int, J: float, T: int, q: int, seed0: int, nchains: int, nsweeps: int):
+    e = np.zeros(nchains, dtype=np.int64)
+    n0 = np.zeros(nchains, dtype=np.int64)
+    if lib().orc_potts_chains(L, J, T, q, seed0, nchains, nsweeps, _p(e), _p(n0)) != 0:
+        raise MemoryError("oracle potts chains: allocation failed")
+    return e, n0

@@ -315,3 +315,141 @@ int orc_one_step_codes(int32_t L, uint32_t T, uint64_t seed0, int64_t nseeds,
     }
     return 0;
 }
+
+/* ================================================================== */
+/* q-state Potts model, the paper's other named target of the same     */
+/* method (Sec. 1, Sec. 6): H = -J sum_<ij> delta(s_i, s_j) with spins  */
+/* 0..q-1.  One sweep is the same three steps: an edge with equal end  */
+/* spins is bonded with p = 1 - exp(-beta J) (one coupling per equal   */
+/* pair; q = 2 is the Ising model at half the coupling), clusters are  */
+/* the components of the bond graph, and every cluster draws a new     */
+/* value uniformly from 0..q-1.                                        */
+/* ================================================================== */
+uint32_t orc_potts_threshold(double beta, double J)
+{
+    double p = -expm1(-beta * J);
+    if (!(p > 0.0)) return 0u;
+    double scaled = floor(ldexp(p, 32));
+    if (scaled >= 4294967296.0) return 0xFFFFFFFFu;
+    return (uint32_t)scaled;
+}
+
+/* A value in 0..q-1 from a uniform 32-bit word: floor(w q / 2^32). */
+static int8_t potts_value(uint32_t w, uint32_t q)
+{
+    return (int8_t)(((uint64_t)w * q) >> 32);
+}
+
+/* Hot start: value of word 0 for counter {s, 0, 2, 0}; cold: all 0. */
+void orc_potts_init(int32_t L, uint64_t seed, int32_t q, int32_t cold, int8_t *spins)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    for (uint32_t s = 0; s < n; ++s) {
+        if (cold) { spins[s] = 0; continue; }
+        uint32_t r[4];
+        philox_seed(seed, s, 0u, 2u, r);
+        spins[s] = potts_value(r[0], (uint32_t)q);
+    }
+}
+
+/* New value of the cluster whose smallest site is r in sweep t: word r mod 4
+ * of the output for counter {r >> 2, t, 3, 0}. */
+int32_t orc_potts_spin(uint64_t seed, uint32_t t, uint32_t root, int32_t q)
+{
+    uint32_t r[4];
+    philox_seed(seed, root >> 2, t, 3u, r);
+    return potts_value(r[root & 3u], (uint32_t)q);
+}
+
+void orc_potts_assign(int32_t L, uint64_t seed, uint32_t t, int32_t q, const uint32_t *labels,
+                      int8_t *spins)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    for (uint32_t s = 0; s < n; ++s)
+        spins[s] = (int8_t)orc_potts_spin(seed, t, labels[s], q);
+}
+
+/* Measurement: e_sum = number of the 2N torus edges whose ends are equal
+ * (H = -J e_sum); m_sum = population of the most populated value; cluster
+ * statistics as for the Ising model. */
+void orc_potts_observe(int32_t L, double J, int32_t q, uint64_t sweep, const int8_t *spins,
+                       const uint32_t *labels, orc_obs *rec, uint64_t *dense)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    int64_t e = 0;
+    int64_t count[256] = {0};
+    for (uint32_t s = 0; s < n; ++s) {
+        e += spins[s] == spins[east_of(s, (uint32_t)L)];
+        e += spins[s] == spins[north_of(s, (uint32_t)L)];
+        count[(uint8_t)spins[s]] += 1;
+    }
+    /* cluster statistics exactly as for the Ising model */
+    orc_observe(L, J, sweep, spins, labels, rec, dense);
+    int64_t m = 0;
+    for (int32_t k = 0; k < q; ++k)
+        if (count[k] > m) m = count[k];
+    rec->e_sum = e;
+    rec->energy = -J * (double)e;
+    rec->m_sum = m;
+}
+
+int orc_potts_sweep(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed, uint32_t t,
+                    int8_t *spins, uint32_t *labels, orc_obs *rec)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    uint8_t *b = (uint8_t *)malloc(n);
+    uint32_t *lab = labels ? labels : (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!b || !lab) {
+        free(b);
+        if (!labels) free(lab);
+        return -1;
+    }
+    orc_bonds(L, T, seed, t, spins, b);
+    orc_label(L, b, lab);
+    orc_potts_assign(L, seed, t, q, lab, spins);
+    if (rec) orc_potts_observe(L, J, q, t, spins, lab, rec, NULL);
+    free(b);
+    if (!labels) free(lab);
+    return 0;
+}
+
+int orc_potts_run(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed, uint32_t t0,
+                  int64_t count, int8_t *spins, orc_obs *recs)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    uint32_t *lab = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!lab) return -1;
+    for (int64_t i = 0; i < count; ++i) {
+        if (orc_potts_sweep(L, J, T, q, seed, t0 + (uint32_t)i, spins, lab, recs ? &recs[i] : NULL) != 0) {
+            free(lab);
+            return -1;
+        }
+    }
+    free(lab);
+    return 0;
+}
+
+/* Ensemble helper: independent hot-start chains (seeds seed0, seed0+1, ...),
+ * `nsweeps` sweeps each; final e_sum (equal pairs) and the count of value 0. */
+int orc_potts_chains(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed0, int64_t nchains,
+                     int32_t nsweeps, int64_t *e_out, int64_t *n0_out)
+{
+    uint32_t n = (uint32_t)L * (uint32_t)L;
+    int8_t *sp = (int8_t *)malloc(n);
+    if (!sp) return -1;
+    for (int64_t c = 0; c < nchains; ++c) {
+        uint64_t seed = seed0 + (uint64_t)c;
+        orc_potts_init(L, seed, q, 0, sp);
+        if (orc_potts_run(L, J, T, q, seed, 0u, nsweeps, sp, NULL) != 0) { free(sp); return -1; }
+        int64_t e = 0, z = 0;
+        for (uint32_t s = 0; s < n; ++s) {
+            e += sp[s] == sp[east_of(s, (uint32_t)L)];
+            e += sp[s] == sp[north_of(s, (uint32_t)L)];
+            z += sp[s] == 0;
+        }
+        e_out[c] = e;
+        n0_out[c] = z;
+    }
+    free(sp);
+    return 0;
+}

@@ -47,6 +47,21 @@ int orc_chains(int32_t L, double J, uint32_t T, uint64_t seed0, int64_t nchains,
 int orc_one_step_codes(int32_t L, uint32_t T, uint64_t seed0, int64_t nseeds,
                        uint32_t t, const int8_t *start, uint64_t *codes);
 
+/* q-state Potts model (spins 0..q-1, q <= 127): see sw_oracle.c. */
+uint32_t orc_potts_threshold(double beta, double J);
+void orc_potts_init(int32_t L, uint64_t seed, int32_t q, int32_t cold, int8_t *spins);
+int32_t orc_potts_spin(uint64_t seed, uint32_t t, uint32_t root, int32_t q);
+void orc_potts_assign(int32_t L, uint64_t seed, uint32_t t, int32_t q, const uint32_t *labels,
+                      int8_t *spins);
+void orc_potts_observe(int32_t L, double J, int32_t q, uint64_t sweep, const int8_t *spins,
+                       const uint32_t *labels, orc_obs *rec, uint64_t *dense);
+int orc_potts_sweep(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed, uint32_t t,
+                    int8_t *spins, uint32_t *labels, orc_obs *rec);
+int orc_potts_run(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed, uint32_t t0,
+                  int64_t count, int8_t *spins, orc_obs *recs);
+int orc_potts_chains(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed0, int64_t nchains,
+                     int32_t nsweeps, int64_t *e_out, int64_t *n0_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import test_oracle_pins as pins
+import test_oracle_potts as potts
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "sw_oracle.c")
 BETA_C = pins.BETA_C
@@ -41,6 +42,15 @@ MUTANTS = [
      "spins[s] = (r[0] & 1u) ? (int8_t)1 : (int8_t)-1;", [pins.test_init_hot_and_cold]),
     ("bond ignores the spins", "if (spins[s] == spins[east_of(s, (uint32_t)L)] && wE < T)", "if (wE < T)",
      [lambda: pins.test_bond_keying_and_rule(5), pins.test_4x4_exact_enumeration_chi2]),
+    ("Potts p with the Ising factor 2", "double p = -expm1(-beta * J);", "double p = -expm1(-2.0 * beta * J);",
+     [potts.test_threshold_closed_form, potts.test_q2_is_ising_at_half_the_coupling]),
+    ("Potts value misses one state", "return (int8_t)(((uint64_t)w * q) >> 32);",
+     "return (int8_t)(((uint64_t)w * (q - 1u)) >> 32);",
+     [potts.test_init_and_value_ranges, potts.test_infinite_temperature_gives_iid_uniform_values]),
+    ("Potts energy drops the N edges", "        e += spins[s] == spins[north_of(s, (uint32_t)L)];\n", "",
+     [potts.test_infinite_temperature_gives_iid_uniform_values, potts.test_q3_critical_energy]),
+    ("Potts cluster value from word 0", "return potts_value(r[root & 3u], (uint32_t)q);",
+     "return potts_value(r[0], (uint32_t)q);", [potts.test_infinite_temperature_gives_iid_uniform_values]),
 ]
 
 

@@ -218,6 +218,22 @@ def label_equivalence(args, tile_rate):
         res["tile_over_label_equivalence"] = res["tile"] / res["label_equivalence"]
         out[f"L{L}_beta{beta:.4f}"] = res
         print(f"[bench] label equivalence L={L}: {res}", file=sys.stderr, flush=True)
+    # the q = 3 Potts model (same path) at its critical point ln(1 + sqrt 3)
+    q = 3
+    beta_q = math.log(1.0 + math.sqrt(q))
+    for L in (4096, args.L):
+        s = sw.Sim(L, beta_q, 1.0, 11, q=q, flags=sw.SW_FLAG_LABEL_EQUIV)
+        s.sweep(3)
+        s.sync()
+        t0 = time.perf_counter()
+        s.sweep(args.le_steps)
+        s.sync()
+        dt = time.perf_counter() - t0
+        rec = s.observables()
+        out[f"potts_q3_L{L}"] = {"value": L * L * args.le_steps / dt, "passes_last_sweep": s.label_passes,
+                                 "energy_per_site": float(rec["energy"]) / (L * L)}
+        s.close()
+        print(f"[bench] Potts q=3 L={L}: {out[f'potts_q3_L{L}']}", file=sys.stderr, flush=True)
     out["unit"] = "site-updates/s"
     return out
 

@@ -92,6 +92,8 @@ typedef struct {
     double J;
     uint64_t seed;
     int64_t ring;
+    int32_t q;     /* 0: Ising (spins +-1); 2..8: q-state Potts (see below) */
+    int32_t reserved;
 } sw_config;
 
 /* Fills *cfg with the given lattice and model and default options
@@ -186,6 +188,17 @@ int sw_get_labels(sw_sim *sim, uint32_t *host, int64_t n);
  * sweep (waits for the stream), -2 if that sweep stopped at the pass limit
  * (65,536) without converging, -1 for a sim of the default path. */
 int32_t sw_label_passes(sw_sim *sim);
+
+/* q-state Potts model (sw_config.q = 2..8, needs SW_FLAG_LABEL_EQUIV): spins
+ * are 0..q-1 (int8), H = -J sum_<ij> delta(s_i, s_j).  A sweep bonds equal
+ * neighbours with p = 1 - exp(-beta J) (T = floor(p 2^32), the same edge
+ * words as the Ising model), forms clusters the same way, and gives every
+ * cluster the value floor(w q / 2^32) of word r mod 4 of the Philox output
+ * for counter {r >> 2, t, 3, 0}, r its smallest site.  Hot start: value of
+ * word 0 for counter {s, 0, 2, 0}; cold start: all 0.  Records: e_sum =
+ * number of the 2N edges with equal ends (energy = -J e_sum), m_sum =
+ * population of the most populated value; cluster statistics as for Ising.
+ * sw_set_spins takes values 0..q-1. */
 
 /* The bond threshold T of this sim (so callers can check it). */
 uint32_t sw_threshold(const sw_sim *sim);

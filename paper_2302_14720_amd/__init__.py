@@ -48,6 +48,8 @@ class sw_config(ctypes.Structure):
         ("J", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("ring", ctypes.c_int64),
+        ("q", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -156,10 +158,10 @@ def _ptr(a: np.ndarray):
 
 # ------------------------------------------------------------- C-named calls
 def sw_config_init(L: int, beta: float, J: float = 1.0, seed: int = 0, *, init: int = SW_INIT_HOT,
-                   tile: int = 0, flags: int = 0, ring: int = 0) -> sw_config:
+                   tile: int = 0, flags: int = 0, ring: int = 0, q: int = 0) -> sw_config:
     cfg = sw_config()
     _check(lib().sw_config_init(ctypes.byref(cfg), L, beta, J, seed))
-    cfg.init, cfg.tile, cfg.flags, cfg.ring = init, tile, flags, ring
+    cfg.init, cfg.tile, cfg.flags, cfg.ring, cfg.q = init, tile, flags, ring, q
     return cfg
 
 
@@ -331,13 +333,13 @@ class Sim:
     """One lattice on the current GPU; workspace and stream come from torch."""
 
     def __init__(self, L: int, beta: float, J: float = 1.0, seed: int = 0, *, init: int = SW_INIT_HOT,
-                 tile: int = 0, flags: int = 0, ring: int = 0, device=None):
+                 tile: int = 0, flags: int = 0, ring: int = 0, q: int = 0, device=None):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("Sim needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.L, self.N = L, L * L
-        self.cfg = sw_config_init(L, beta, J, seed, init=init, tile=tile, flags=flags, ring=ring)
+        self.cfg = sw_config_init(L, beta, J, seed, init=init, tile=tile, flags=flags, ring=ring, q=q)
         nbytes = sw_workspace_bytes_ex(self.cfg)
         if nbytes == 0:
             # same validation as create, for the error message

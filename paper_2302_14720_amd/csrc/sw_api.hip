@@ -72,6 +72,10 @@ int validate(const sw_config *c) {
     if ((c->flags & ~(SW_FLAG_LABELS | SW_FLAG_DENSE_HIST | SW_FLAG_LABEL_EQUIV)) != 0u)
         return fail(SW_EINVAL, "unknown flag bits");
     if (c->ring < 0 || c->ring > (int64_t)1 << 30) return fail(SW_EINVAL, "ring must be in [0, 2^30]");
+    if (c->q != 0 && (c->q < 2 || c->q > swmi::kMaxQ))
+        return fail(SW_EINVAL, "q must be 0 (Ising) or in [2, 8] (Potts)");
+    if (c->q != 0 && !(c->flags & SW_FLAG_LABEL_EQUIV))
+        return fail(SW_EINVAL, "the q-state Potts model runs on the label-equivalence path (SW_FLAG_LABEL_EQUIV)");
     return SW_OK;
 }
 
@@ -128,7 +132,10 @@ Dev make_dev(const sw_config &c, char *base, const Layout &lo) {
     d.ntx = d.L / d.tw;
     d.ntiles = d.ntx * d.ntx;
     d.ngroups = (d.ntiles + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
-    d.T = bond_threshold(c.beta, c.J);
+    // Potts coupling: one J per equal pair, p = 1 - exp(-beta J) (the Ising
+    // threshold at half the coupling)
+    d.q = (uint32_t)c.q;
+    d.T = c.q ? bond_threshold(0.5 * c.beta, c.J) : bond_threshold(c.beta, c.J);
     d.seed_lo = (uint32_t)(c.seed & 0xFFFFFFFFu);
     d.seed_hi = (uint32_t)(c.seed >> 32);
     d.ring_cap = (uint32_t)c.ring;
@@ -498,8 +505,11 @@ int sw_get_spins(sw_sim *s, int8_t *host, int64_t n) {
 int sw_set_spins(sw_sim *s, const int8_t *host, int64_t n, uint64_t next_sweep) {
     if (!s || !host) return fail(SW_EINVAL, "sim or host is NULL");
     if (n != (int64_t)s->dev.L * s->dev.L) return fail(SW_ERANGE, "n must equal L*L");
-    for (int64_t i = 0; i < n; ++i)
-        if (host[i] != 1 && host[i] != -1) return fail(SW_EINVAL, "spins must be +1 or -1");
+    const int32_t q = s->cfg.q;
+    for (int64_t i = 0; i < n; ++i) {
+        if (q == 0 && host[i] != 1 && host[i] != -1) return fail(SW_EINVAL, "spins must be +1 or -1");
+        if (q != 0 && (host[i] < 0 || host[i] >= q)) return fail(SW_EINVAL, "Potts spins must be in 0..q-1");
+    }
     int rc = ensure_device(s);
     if (rc != SW_OK) return rc;
     HIP_TRY(hipStreamSynchronize(s->stream));

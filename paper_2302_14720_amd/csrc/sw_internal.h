@@ -31,7 +31,8 @@ namespace swmi {
 
 constexpr uint32_t kNodeSlots = 256;  // node slots per tile (64x64 tile: <= 252 nodes)
 constexpr int kTilePart = 32;         // int32 words of a per-tile partial
-constexpr int kGroupPart = 40;        // uint64 words of a per-group partial
+constexpr int kGroupPart = 48;        // uint64 words of a per-group partial
+constexpr int kMaxQ = 8;              // largest q of the Potts model
 constexpr int kAccWords = 64;         // record accumulator + completion counter
 constexpr int kGroupTiles = 16;       // tiles per workgroup in k_flatten / k_roots
 constexpr uint32_t kUG = 4;           // side, in tiles, of a k_ulocal group
@@ -39,7 +40,8 @@ constexpr uint32_t kUG = 4;           // side, in tiles, of a k_ulocal group
 // tile partial (int32 words)
 enum { TP_E = 0, TP_M = 1, TP_N = 2, TP_MAX = 3, TP_SQ = 4, TP_HIST = 5 };  // hist: 12 bins
 // group partial / accumulator (uint64 words)
-enum { GP_N = 0, GP_MAX = 1, GP_SQ = 2, GP_E = 3, GP_M = 4, GP_HIST = 5, GP_END = 38 };
+// GP_CNT..: population of each Potts value
+enum { GP_N = 0, GP_MAX = 1, GP_SQ = 2, GP_E = 3, GP_M = 4, GP_HIST = 5, GP_CNT = 38, GP_END = 46 };
 enum { ACC_COUNT = 48 };
 
 struct Dev {
@@ -67,6 +69,7 @@ struct Dev {
     uint32_t T, seed_lo, seed_hi;
     uint32_t ring_cap;
     uint32_t le_grid;     // workgroups of the cooperative labelling kernel (0: tile path)
+    uint32_t q;           // 0: Ising; 2..kMaxQ: q-state Potts (label-equivalence path)
     double J;
 };
 

@@ -1059,7 +1059,12 @@ __device__ __forceinline__ void record_write(const Dev &d, const uint64_t *s_acc
         const int64_t e = (int64_t)s_acc[GP_E];
         rec->e_sum = e;
         rec->energy = -d.J * (double)e;
-        rec->m_sum = (int64_t)s_acc[GP_M];
+        int64_t m = (int64_t)s_acc[GP_M];
+        if (d.q) {  // Potts: population of the most populated value
+            m = 0;
+            for (uint32_t k = 0; k < d.q; ++k) m = max(m, (int64_t)s_acc[GP_CNT + k]);
+        }
+        rec->m_sum = m;
     }
     __syncthreads();  // every thread has read the sweep index
     if (tid == 0u) {
@@ -1215,19 +1220,24 @@ __global__ __launch_bounds__(TW *TW / 16) void k_resolve_b(const Dev *devs, cons
 }
 
 // Initial spins (Fig. 1): hot = bit 0 of word 0 of Philox({s, 0, 2, 0}),
-// cold = all +1.  16 sites per thread.
+// cold = all +1; for the Potts model hot = floor(w q / 2^32) of that word,
+// cold = all 0.  16 sites per thread.
 __global__ __launch_bounds__(256) void k_init(Dev d, int cold) {
     const size_t n16 = (size_t)d.L * d.L / 16u;
     const uint32_t pc = (uint32_t)(*d.tdev & 1u);
     int8_t *sp = d.spins[pc];
+    const uint32_t fill = d.q ? 0u : 0x01010101u;
     for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256) {
-        uint32_t out[4] = {0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u};
+        uint32_t out[4] = {fill, fill, fill, fill};
         if (!cold) {
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 uint32_t w0 = (uint32_t)(i * 16u + q), w1 = 0u, w2 = 2u, w3 = 0u;
                 philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
-                if (w0 & 1u) out[q >> 2] |= 0xFFu << (8 * (q & 3));
+                if (d.q)
+                    out[q >> 2] |= (uint32_t)(((uint64_t)w0 * d.q) >> 32) << (8 * (q & 3));
+                else if (w0 & 1u)
+                    out[q >> 2] |= 0xFFu << (8 * (q & 3));
             }
         }
         *reinterpret_cast<uint4 *>(sp + i * 16u) = make_uint4(out[0], out[1], out[2], out[3]);

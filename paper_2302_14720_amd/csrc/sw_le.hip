@@ -119,15 +119,16 @@ __global__ __launch_bounds__(256) void k_le_label(Dev d) {
     }
 }
 
-// New spin of every cluster (Sec. 2.4) at its root; sizes cleared.  A
-// wavefront's 64 sites lie in one 128-site block, so the Philox call of the
-// cluster-spin rule is the same for all its lanes.
+// New spin of every cluster (Sec. 2.4) at its root; sizes cleared.  For the
+// Ising model a wavefront's 64 sites lie in one 128-site block, so the
+// Philox call of the cluster-spin rule is the same for all its lanes.
 __global__ __launch_bounds__(256) void k_le_roots(Dev d) {
     const size_t N = (size_t)d.L * d.L;
     const uint32_t t = (uint32_t)*d.tdev;
     for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < N; i += (size_t)gridDim.x * 256) {
         if (d.labels[i] != (uint32_t)i) continue;
-        d.le_rsp[i] = cluster_spin((uint32_t)i, t, d.seed_lo, d.seed_hi);
+        d.le_rsp[i] = d.q ? potts_spin((uint32_t)i, t, d.q, d.seed_lo, d.seed_hi)
+                          : cluster_spin((uint32_t)i, t, d.seed_lo, d.seed_hi);
         d.le_cnt[i] = 0u;
     }
 }
@@ -182,13 +183,21 @@ __global__ __launch_bounds__(256) void k_le_stats(Dev d) {
     const int8_t *sp = d.spins[0];
     int64_t e = 0, m = 0;
     uint64_t n = 0, mx = 0, sq = 0;
+    __shared__ unsigned int s_cnt[kMaxQ];
+    if (threadIdx.x < (uint32_t)kMaxQ) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
     for (size_t i = b0 + threadIdx.x; i < b1; i += 256u) {
         const uint32_t y = (uint32_t)(i / L), x = (uint32_t)(i % L);
         const int32_t si = sp[i];
         const int32_t se = sp[(size_t)y * L + (x + 1u == L ? 0u : x + 1u)];
         const int32_t sn = sp[(size_t)(y + 1u == L ? 0u : y + 1u) * L + x];
-        e += si * se + si * sn;
-        m += si;
+        if (d.q) {  // Potts: equal pairs and value populations
+            e += (si == se) + (si == sn);
+            atomicAdd(&s_cnt[(uint32_t)si < (uint32_t)kMaxQ ? si : 0], 1u);
+        } else {
+            e += si * se + si * sn;
+            m += si;
+        }
         if (d.labels[i] == (uint32_t)i) {
             const uint32_t S = d.le_cnt[i];
             ++n;
@@ -213,6 +222,8 @@ __global__ __launch_bounds__(256) void k_le_stats(Dev d) {
         atomicMax(&s_acc[GP_MAX], (unsigned long long)mx);
         atomicAdd(&s_acc[GP_SQ], (unsigned long long)sq);
     }
+    __syncthreads();
+    if (threadIdx.x < (uint32_t)kMaxQ) s_acc[GP_CNT + threadIdx.x] = s_cnt[threadIdx.x];
     __syncthreads();
     uint64_t *gp = d.gpart + (size_t)blockIdx.x * kGroupPart;
     for (uint32_t i = threadIdx.x; i < (uint32_t)GP_END; i += 256u) gp[i] = s_acc[i];

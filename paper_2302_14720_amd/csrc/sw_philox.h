@@ -37,4 +37,15 @@ __device__ __forceinline__ int8_t cluster_spin(uint32_t r, uint32_t t, uint32_t 
     return ((w >> (r & 31u)) & 1u) ? (int8_t)-1 : (int8_t)1;
 }
 
+// New value (0..q-1) of the Potts cluster whose smallest site is r in sweep
+// t: floor(w q / 2^32) of word r mod 4 of the output for counter
+// {r >> 2, t, 3, 0}.
+__device__ __forceinline__ int8_t potts_spin(uint32_t r, uint32_t t, uint32_t q, uint32_t k0, uint32_t k1) {
+    uint32_t w0 = r >> 2, w1 = t, w2 = 3u, w3 = 0u;
+    philox10(w0, w1, w2, w3, k0, k1);
+    const uint32_t qq = r & 3u;
+    const uint32_t w = qq == 0 ? w0 : qq == 1 ? w1 : qq == 2 ? w2 : w3;
+    return (int8_t)(((uint64_t)w * q) >> 32);
+}
+
 }  // namespace swmi

@@ -88,6 +88,20 @@ def _bind(l: ctypes.CDLL) -> ctypes.CDLL:
     l.orc_potts_run.restype = ctypes.c_int
     l.orc_potts_chains.argtypes = [i32, f64, u32, i32, u64, i64, i32, P, P]
     l.orc_potts_chains.restype = ctypes.c_int
+    l.orc_cubic_init.argtypes = [i32, u64, i32, i32, P]
+    l.orc_cubic_init.restype = None
+    l.orc_cubic_bonds.argtypes = [i32, u32, u64, u32, P, P]
+    l.orc_cubic_bonds.restype = None
+    l.orc_cubic_label.argtypes = [i32, P, P]
+    l.orc_cubic_label.restype = None
+    l.orc_cubic_observe.argtypes = [i32, f64, i32, u64, P, P, P, P]
+    l.orc_cubic_observe.restype = None
+    l.orc_cubic_sweep.argtypes = [i32, f64, u32, i32, u64, u32, P, P, P, P, P]
+    l.orc_cubic_sweep.restype = ctypes.c_int
+    l.orc_cubic_run.argtypes = [i32, f64, u32, i32, u64, u32, i64, P, P]
+    l.orc_cubic_run.restype = ctypes.c_int
+    l.orc_cubic_chains.argtypes = [i32, f64, u32, i32, u64, i64, i32, P, P]
+    l.orc_cubic_chains.restype = ctypes.c_int
     return l
 
 
@@ -274,3 +288,73 @@ def potts_chains(L: int, J: float, T: int, q: int, seed0: int, nchains: int, nsw
     if lib().orc_potts_chains(L, J, T, q, seed0, nchains, nsweeps, _p(e), _p(n0)) != 0:
         raise MemoryError("oracle potts chains: allocation failed")
     return e, n0
+
+
+# ------------------------------------------------------- simple cubic lattice
+# L x L x L sites, s = (z*L + y)*L + x; q = 0 is the Ising model (threshold
+# ``threshold``), q = 2..8 the Potts model (threshold ``potts_threshold``).
+def cubic_init(L: int, seed: int, q: int = 0, cold: bool = False) -> np.ndarray:
+    s = np.empty(L ** 3, dtype=np.int8)
+    lib().orc_cubic_init(L, seed, q, 1 if cold else 0, _p(s))
+    return s
+
+
+def cubic_bonds(L: int, T: int, seed: int, t: int, spins: np.ndarray) -> np.ndarray:
+    sp = np.ascontiguousarray(spins, dtype=np.int8)
+    assert sp.size == L ** 3
+    b = np.empty(L ** 3, dtype=np.uint8)
+    lib().orc_cubic_bonds(L, T, seed, t, _p(sp), _p(b))
+    return b
+
+
+def cubic_label(L: int, bond_mask: np.ndarray) -> np.ndarray:
+    b = np.ascontiguousarray(bond_mask, dtype=np.uint8)
+    assert b.size == L ** 3
+    lab = np.empty(L ** 3, dtype=np.uint32)
+    lib().orc_cubic_label(L, _p(b), _p(lab))
+    return lab
+
+
+def cubic_observe(L: int, J: float, q: int, sweep: int, spins: np.ndarray, labels=None,
+                  dense: bool = False):
+    sp = np.ascontiguousarray(spins, dtype=np.int8)
+    lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.uint32)
+    rec = np.zeros(1, dtype=OBS_DTYPE)
+    d = np.zeros(L ** 3 + 1, dtype=np.uint64) if dense else None
+    lib().orc_cubic_observe(L, J, q, sweep, _p(sp), _p(lab), _p(rec), _p(d))
+    return (rec[0], d) if dense else rec[0]
+
+
+def cubic_sweep(L: int, J: float, T: int, q: int, seed: int, t: int, spins: np.ndarray,
+                dense: bool = False):
+    """One sweep in place on ``spins``; returns (record, labels, bonds[, dense])."""
+    n = L ** 3
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous and spins.size == n
+    lab = np.empty(n, dtype=np.uint32)
+    b = np.empty(n, dtype=np.uint8)
+    rec = np.zeros(1, dtype=OBS_DTYPE)
+    d = np.zeros(n + 1, dtype=np.uint64) if dense else None
+    if lib().orc_cubic_sweep(L, J, T, q, seed, t, _p(spins), _p(lab), _p(b), _p(rec), _p(d)) != 0:
+        raise MemoryError("oracle cubic sweep: allocation failed")
+    if dense:
+        return rec[0], lab, b, d
+    return rec[0], lab, b
+
+
+def cubic_run(L: int, J: float, T: int, q: int, seed: int, t0: int, count: int,
+              spins: np.ndarray) -> np.ndarray:
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous and spins.size == L ** 3
+    recs = np.zeros(count, dtype=OBS_DTYPE)
+    if lib().orc_cubic_run(L, J, T, q, seed, t0, count, _p(spins), _p(recs)) != 0:
+        raise MemoryError("oracle cubic run: allocation failed")
+    return recs
+
+
+def cubic_chains(L: int, J: float, T: int, q: int, seed0: int, nchains: int, nsweeps: int):
+    """Final e_sum and m_sum (Ising) or count of value 0 (Potts) of
+    independent hot-start chains."""
+    e = np.zeros(nchains, dtype=np.int64)
+    m = np.zeros(nchains, dtype=np.int64)
+    if lib().orc_cubic_chains(L, J, T, q, seed0, nchains, nsweeps, _p(e), _p(m)) != 0:
+        raise MemoryError("oracle cubic chains: allocation failed")
+    return e, m

@@ -187,6 +187,8 @@ void orc_assign(int32_t L, uint64_t seed, uint32_t t, const uint32_t *labels,
         spins[s] = (int8_t)orc_flip_spin(seed, t, labels[s]);
 }
 
+static void cluster_stats(uint32_t n, const uint32_t *labels, orc_obs *rec, uint64_t *dense);
+
 /* Sec. 2.5 measurement: H = -J sum_<ij> s_i s_j over the 2N torus edges,
  * M = sum_i s_i (the paper divides by N; the exact integer sum is kept and
  * divided at the end).  Cluster statistics come from the labels of the
@@ -208,6 +210,15 @@ void orc_observe(int32_t L, double J, uint64_t sweep, const int8_t *spins,
     rec->e_sum = e;
     rec->energy = -J * (double)e;
     rec->m_sum = m;
+    cluster_stats(n, labels, rec, dense);
+}
+
+/* Cluster statistics of a labelling of n sites (each label the smallest
+ * site of its cluster): count, largest size, sum of squared sizes and the
+ * log2-binned size histogram; `dense` (may be NULL) receives counts[size]
+ * for size = 0..n. */
+static void cluster_stats(uint32_t n, const uint32_t *labels, orc_obs *rec, uint64_t *dense)
+{
     if (dense) memset(dense, 0, sizeof(uint64_t) * ((size_t)n + 1u));
     if (!labels) return;
     uint32_t *size = (uint32_t *)calloc(n, sizeof(uint32_t));
@@ -449,6 +460,169 @@ int orc_potts_chains(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed0,
         }
         e_out[c] = e;
         n0_out[c] = z;
+    }
+    free(sp);
+    return 0;
+}
+
+/* ================================================================== */
+/* Simple cubic lattice, L x L x L, periodic: the other geometry the   */
+/* paper names for the same method (Sec. 6).  The sweep is unchanged:  */
+/* bond equal neighbours with the model's threshold, take connected    */
+/* components, give every cluster a fresh spin (Ising, q = 0) or value  */
+/* (Potts, q = 2..8) keyed by its smallest site, measure.              */
+/*   site index   s = (z*L + y)*L + x, x fastest                       */
+/*   direction d  0: +x, 1: +y, 2: +z; each site owns the three edges  */
+/*                to its +x, +y and +z neighbours (all 3N edges once)  */
+/*   bond word    word d of Philox({s, t, 4, 0}) (one call per site)   */
+/*   hot start    word 0 of Philox({s, 0, 2, 0}), read as in 2D         */
+/*   new spins    orc_flip_spin / orc_potts_spin of the root, as in 2D */
+/* The caller passes the threshold: orc_threshold(beta, J) for the      */
+/* Ising model, orc_potts_threshold(beta, J) for Potts.                 */
+/* ================================================================== */
+static uint32_t cubic_step(uint32_t s, uint32_t L, int d)
+{
+    uint32_t x = s % L, y = (s / L) % L, z = s / L / L;
+    if (d == 0) x = (x + 1u) % L;
+    else if (d == 1) y = (y + 1u) % L;
+    else z = (z + 1u) % L;
+    return (z * L + y) * L + x;
+}
+
+static uint32_t cubic_sites(int32_t L)
+{
+    return (uint32_t)L * (uint32_t)L * (uint32_t)L;
+}
+
+void orc_cubic_init(int32_t L, uint64_t seed, int32_t q, int32_t cold, int8_t *spins)
+{
+    uint32_t n = cubic_sites(L);
+    for (uint32_t s = 0; s < n; ++s) {
+        if (cold) { spins[s] = q ? (int8_t)0 : (int8_t)1; continue; }
+        uint32_t r[4];
+        philox_seed(seed, s, 0u, 2u, r);
+        if (q) spins[s] = potts_value(r[0], (uint32_t)q);
+        else spins[s] = (int8_t)((r[0] & 1u) ? -1 : 1);
+    }
+}
+
+/* bonds[s] bit d = bond (s, step d of s). */
+void orc_cubic_bonds(int32_t L, uint32_t T, uint64_t seed, uint32_t t,
+                     const int8_t *spins, uint8_t *bonds)
+{
+    uint32_t n = cubic_sites(L);
+    for (uint32_t s = 0; s < n; ++s) {
+        uint32_t r[4];
+        philox_seed(seed, s, t, 4u, r);
+        uint8_t b = 0;
+        for (int d = 0; d < 3; ++d) {
+            uint32_t nb = cubic_step(s, (uint32_t)L, d);
+            if (spins[s] == spins[nb] && r[d] < T) b |= (uint8_t)(1u << d);
+        }
+        bonds[s] = b;
+    }
+}
+
+void orc_cubic_label(int32_t L, const uint8_t *bonds, uint32_t *labels)
+{
+    uint32_t n = cubic_sites(L);
+    for (uint32_t s = 0; s < n; ++s) labels[s] = s;
+    for (uint32_t s = 0; s < n; ++s)
+        for (int d = 0; d < 3; ++d)
+            if (bonds[s] & (1u << d)) uf_union(labels, s, cubic_step(s, (uint32_t)L, d));
+    for (uint32_t s = 0; s < n; ++s) labels[s] = uf_find(labels, s);
+}
+
+/* Ising: e_sum = sum over the 3N edges of s_i s_j, m_sum = sum of s_i.
+ * Potts: e_sum = number of the 3N edges with equal ends, m_sum = population
+ * of the most populated value.  Cluster statistics as in 2D. */
+void orc_cubic_observe(int32_t L, double J, int32_t q, uint64_t sweep, const int8_t *spins,
+                       const uint32_t *labels, orc_obs *rec, uint64_t *dense)
+{
+    uint32_t n = cubic_sites(L);
+    int64_t e = 0, m = 0;
+    int64_t count[256] = {0};
+    for (uint32_t s = 0; s < n; ++s) {
+        for (int d = 0; d < 3; ++d) {
+            int8_t o = spins[cubic_step(s, (uint32_t)L, d)];
+            e += q ? (int64_t)(spins[s] == o) : (int64_t)spins[s] * o;
+        }
+        m += spins[s];
+        count[(uint8_t)spins[s]] += 1;
+    }
+    if (q) {
+        m = 0;
+        for (int32_t k = 0; k < q; ++k)
+            if (count[k] > m) m = count[k];
+    }
+    memset(rec, 0, sizeof(*rec));
+    rec->sweep = sweep;
+    rec->e_sum = e;
+    rec->energy = -J * (double)e;
+    rec->m_sum = m;
+    cluster_stats(n, labels, rec, dense);
+}
+
+int orc_cubic_sweep(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed, uint32_t t,
+                    int8_t *spins, uint32_t *labels, uint8_t *bonds, orc_obs *rec, uint64_t *dense)
+{
+    uint32_t n = cubic_sites(L);
+    uint8_t *b = bonds ? bonds : (uint8_t *)malloc(n);
+    uint32_t *lab = labels ? labels : (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!b || !lab) {
+        if (!bonds) free(b);
+        if (!labels) free(lab);
+        return -1;
+    }
+    orc_cubic_bonds(L, T, seed, t, spins, b);
+    orc_cubic_label(L, b, lab);
+    for (uint32_t s = 0; s < n; ++s)
+        spins[s] = (int8_t)(q ? orc_potts_spin(seed, t, lab[s], q) : orc_flip_spin(seed, t, lab[s]));
+    if (rec) orc_cubic_observe(L, J, q, t, spins, lab, rec, dense);
+    if (!bonds) free(b);
+    if (!labels) free(lab);
+    return 0;
+}
+
+int orc_cubic_run(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed, uint32_t t0,
+                  int64_t count, int8_t *spins, orc_obs *recs)
+{
+    uint32_t n = cubic_sites(L);
+    uint8_t *b = (uint8_t *)malloc(n);
+    uint32_t *lab = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!b || !lab) { free(b); free(lab); return -1; }
+    for (int64_t i = 0; i < count; ++i) {
+        if (orc_cubic_sweep(L, J, T, q, seed, t0 + (uint32_t)i, spins, lab, b,
+                            recs ? &recs[i] : NULL, NULL) != 0) {
+            free(b);
+            free(lab);
+            return -1;
+        }
+    }
+    free(b);
+    free(lab);
+    return 0;
+}
+
+/* Ensemble helper: independent hot-start chains (seeds seed0, seed0+1, ...),
+ * `nsweeps` sweeps each; final e_sum and m_sum (Ising) or the count of
+ * value 0 (Potts). */
+int orc_cubic_chains(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed0, int64_t nchains,
+                     int32_t nsweeps, int64_t *e_out, int64_t *m_out)
+{
+    uint32_t n = cubic_sites(L);
+    int8_t *sp = (int8_t *)malloc(n);
+    if (!sp) return -1;
+    for (int64_t c = 0; c < nchains; ++c) {
+        uint64_t seed = seed0 + (uint64_t)c;
+        orc_cubic_init(L, seed, q, 0, sp);
+        if (orc_cubic_run(L, J, T, q, seed, 0u, nsweeps, sp, NULL) != 0) { free(sp); return -1; }
+        orc_obs rec;
+        orc_cubic_observe(L, J, q, 0, sp, NULL, &rec, NULL);
+        int64_t z = 0;
+        for (uint32_t s = 0; s < n; ++s) z += sp[s] == 0;
+        e_out[c] = rec.e_sum;
+        m_out[c] = q ? z : rec.m_sum;
     }
     free(sp);
     return 0;

@@ -62,8 +62,23 @@ int orc_potts_run(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed, uin
 int orc_potts_chains(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed0, int64_t nchains,
                      int32_t nsweeps, int64_t *e_out, int64_t *n0_out);
 
+/* simple cubic lattice (L x L x L); q = 0 Ising, 2..8 Potts */
+void orc_cubic_init(int32_t L, uint64_t seed, int32_t q, int32_t cold, int8_t *spins);
+void orc_cubic_bonds(int32_t L, uint32_t T, uint64_t seed, uint32_t t,
+                     const int8_t *spins, uint8_t *bonds);
+void orc_cubic_label(int32_t L, const uint8_t *bonds, uint32_t *labels);
+void orc_cubic_observe(int32_t L, double J, int32_t q, uint64_t sweep, const int8_t *spins,
+                       const uint32_t *labels, orc_obs *rec, uint64_t *dense);
+int orc_cubic_sweep(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed, uint32_t t,
+                    int8_t *spins, uint32_t *labels, uint8_t *bonds, orc_obs *rec, uint64_t *dense);
+int orc_cubic_run(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed, uint32_t t0,
+                  int64_t count, int8_t *spins, orc_obs *recs);
+int orc_cubic_chains(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed0, int64_t nchains,
+                     int32_t nsweeps, int64_t *e_out, int64_t *m_out);
+
 #ifdef __cplusplus
 }
 #endif
+
 
 #endif

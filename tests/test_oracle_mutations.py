@@ -12,6 +12,7 @@ import pytest
 import oracle
 import test_oracle_pins as pins
 import test_oracle_potts as potts
+import test_oracle_cubic as cubic
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "sw_oracle.c")
 BETA_C = pins.BETA_C
@@ -51,6 +52,18 @@ MUTANTS = [
      [potts.test_infinite_temperature_gives_iid_uniform_values, potts.test_q3_critical_energy]),
     ("Potts cluster value from word 0", "return potts_value(r[root & 3u], (uint32_t)q);",
      "return potts_value(r[0], (uint32_t)q);", [potts.test_infinite_temperature_gives_iid_uniform_values]),
+    ("cubic +z step goes to -z", "else z = (z + 1u) % L;", "else z = (z + L - 1u) % L;",
+     [lambda: cubic.test_bond_keying_and_rule(0), lambda: cubic.test_labels_are_min_site_components(5, 0.25)]),
+    ("cubic bond word of the next direction", "spins[s] == spins[nb] && r[d] < T",
+     "spins[s] == spins[nb] && r[(d + 1) % 3] < T", [lambda: cubic.test_bond_keying_and_rule(3)]),
+    ("cubic bonds on the 2D counter tag", "philox_seed(seed, s, t, 4u, r);", "philox_seed(seed, s, t, 0u, r);",
+     [lambda: cubic.test_bond_keying_and_rule(0)]),
+    ("cubic energy skips the +z edges", "for (int d = 0; d < 3; ++d) {\n            int8_t o",
+     "for (int d = 0; d < 2; ++d) {\n            int8_t o",
+     [cubic.test_2x2x2_ising_exact_enumeration_chi2, cubic.test_low_temperature_series]),
+    ("cubic labels skip the +z bonds", "for (int d = 0; d < 3; ++d)\n            if (bonds[s] & (1u << d)) uf_union",
+     "for (int d = 0; d < 2; ++d)\n            if (bonds[s] & (1u << d)) uf_union",
+     [lambda: cubic.test_labels_are_min_site_components(4, 0.3), cubic.test_2x2x2_ising_exact_enumeration_chi2]),
 ]
 
 

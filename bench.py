@@ -194,7 +194,8 @@ def label_equivalence(args, tile_rate):
     """The paper's own cluster formation (iterated label equivalence in
     global memory, one cooperative kernel) against the tile pipeline: the
     same sweeps, bit for bit, at the paper's 512^2 / beta = 0.4 and at the
-    headline lattice."""
+    headline lattice; then the q = 3 Potts model and the simple cubic
+    lattice, which run on that path."""
     import paper_2302_14720_amd as sw
 
     out = {}
@@ -237,6 +238,22 @@ def label_equivalence(args, tile_rate):
                                  "sweeps_from_hot_start": 3 + args.le_steps}
         s.close()
         print(f"[bench] Potts q=3 L={L}: {out[f'potts_q3_L{L}']}", file=sys.stderr, flush=True)
+    # the simple cubic lattice (same path): 3D Ising at its critical coupling
+    # (numerical estimate 0.2216544) and 3D q = 3 Potts near its transition
+    Lc = 512
+    for name, q, beta in (("cubic_ising", 0, 0.2216544), ("cubic_potts_q3", 3, 0.5505)):
+        s = sw.Sim(Lc, beta, 1.0, 13, q=q, dims=3, flags=sw.SW_FLAG_LABEL_EQUIV)
+        s.sweep(3)
+        s.sync()
+        t0 = time.perf_counter()
+        s.sweep(args.le_steps)
+        s.sync()
+        dt = time.perf_counter() - t0
+        key = f"{name}_L{Lc}"
+        out[key] = {"value": Lc ** 3 * args.le_steps / dt, "sites": Lc ** 3, "beta": beta,
+                    "passes_last_sweep": s.label_passes, "sweeps_from_hot_start": 3 + args.le_steps}
+        s.close()
+        print(f"[bench] {key}: {out[key]}", file=sys.stderr, flush=True)
     out["unit"] = "site-updates/s"
     return out
 
@@ -260,7 +277,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--serve-jobs", type=int, default=48, help="jobs of the serving leg (0 = skip)")
     ap.add_argument("--le-steps", type=int, default=10,
-                    help="timed sweeps of the label-equivalence comparison (0 = skip)")
+                    help="timed sweeps of the label-equivalence comparison, its Potts and its "
+                         "simple cubic runs (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the serving leg, jobs/s")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for "

@@ -77,7 +77,8 @@ typedef struct {
     uint64_t hist_log2[33];  /* clusters with size in [2^k, 2^(k+1))           */
 } sw_obs;
 
-/* Creation parameters.  L: lattice side, a multiple of 32 in [32, 32768].
+/* Creation parameters.  L: lattice side, a multiple of 32 in [32, 32768]
+ * (simple cubic lattice: a multiple of 16 in [16, 1616]).
  * beta >= 0 and J > 0, both finite.  init: SW_INIT_HOT or SW_INIT_COLD.
  * tile: 0 (automatic: 64 when L is a multiple of 64, else 32), 32 or 64 --
  * the side of the square tile one workgroup labels in LDS; results do not
@@ -93,7 +94,7 @@ typedef struct {
     uint64_t seed;
     int64_t ring;
     int32_t q;     /* 0: Ising (spins +-1); 2..8: q-state Potts (see below) */
-    int32_t reserved;
+    int32_t dims;  /* 0 or 2: L x L square lattice; 3: L x L x L simple cubic (see below) */
 } sw_config;
 
 /* Fills *cfg with the given lattice and model and default options
@@ -199,6 +200,20 @@ int32_t sw_label_passes(sw_sim *sim);
  * number of the 2N edges with equal ends (energy = -J e_sum), m_sum =
  * population of the most populated value; cluster statistics as for Ising.
  * sw_set_spins takes values 0..q-1. */
+
+/* Simple cubic lattice (sw_config.dims = 3, needs SW_FLAG_LABEL_EQUIV; L a
+ * multiple of 16 in [16, 1616], so that N = L^3 < 2^32): the same sweep on
+ * the L x L x L periodic lattice, for the Ising model (q = 0) and the Potts
+ * model (q = 2..8).  Site s = (z L + y) L + x, x fastest; each site owns the
+ * edges to its +x, +y and +z neighbours (3N edges), and the word of edge
+ * (s, d) is word d (0: +x, 1: +y, 2: +z) of the Philox output for counter
+ * {s, t, 4, 0}.  Thresholds, start states, new spins and records follow the
+ * square-lattice rules, with the sums taken over the 3N edges.  Spin and
+ * label buffers hold N = L^3 entries (sw_sites). */
+
+/* Number of lattice sites N (L^2, or L^3 for the simple cubic lattice);
+ * -1 for NULL. */
+int64_t sw_sites(const sw_sim *sim);
 
 /* The bond threshold T of this sim (so callers can check it). */
 uint32_t sw_threshold(const sw_sim *sim);

@@ -49,7 +49,7 @@ class sw_config(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("ring", ctypes.c_int64),
         ("q", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("dims", ctypes.c_int32),
     ]
 
 
@@ -98,6 +98,7 @@ _SIGNATURES = {
     "sw_next_sweep": (ctypes.c_int64, [_P]),
     "sw_lattice": (ctypes.c_int32, [_P]),
     "sw_tile": (ctypes.c_int32, [_P]),
+    "sw_sites": (ctypes.c_int64, [_P]),
     "sw_destroy": (None, [_P]),
     "sw_last_error": (ctypes.c_char_p, []),
     "sw_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32]),
@@ -158,10 +159,10 @@ def _ptr(a: np.ndarray):
 
 # ------------------------------------------------------------- C-named calls
 def sw_config_init(L: int, beta: float, J: float = 1.0, seed: int = 0, *, init: int = SW_INIT_HOT,
-                   tile: int = 0, flags: int = 0, ring: int = 0, q: int = 0) -> sw_config:
+                   tile: int = 0, flags: int = 0, ring: int = 0, q: int = 0, dims: int = 0) -> sw_config:
     cfg = sw_config()
     _check(lib().sw_config_init(ctypes.byref(cfg), L, beta, J, seed))
-    cfg.init, cfg.tile, cfg.flags, cfg.ring, cfg.q = init, tile, flags, ring, q
+    cfg.init, cfg.tile, cfg.flags, cfg.ring, cfg.q, cfg.dims = init, tile, flags, ring, q, dims
     return cfg
 
 
@@ -333,13 +334,14 @@ class Sim:
     """One lattice on the current GPU; workspace and stream come from torch."""
 
     def __init__(self, L: int, beta: float, J: float = 1.0, seed: int = 0, *, init: int = SW_INIT_HOT,
-                 tile: int = 0, flags: int = 0, ring: int = 0, q: int = 0, device=None):
+                 tile: int = 0, flags: int = 0, ring: int = 0, q: int = 0, dims: int = 2, device=None):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("Sim needs a ROCm GPU (torch.cuda.is_available() is False)")
-        self.L, self.N = L, L * L
-        self.cfg = sw_config_init(L, beta, J, seed, init=init, tile=tile, flags=flags, ring=ring, q=q)
+        self.L, self.N = L, L ** (3 if dims == 3 else 2)
+        self.cfg = sw_config_init(L, beta, J, seed, init=init, tile=tile, flags=flags, ring=ring, q=q,
+                                  dims=dims)
         nbytes = sw_workspace_bytes_ex(self.cfg)
         if nbytes == 0:
             # same validation as create, for the error message

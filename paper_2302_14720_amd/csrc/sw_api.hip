@@ -60,15 +60,28 @@ int resolve_tile(const sw_config &c) {
     return c.tile;
 }
 
+size_t sites_of(const sw_config &c) {
+    const size_t L = (size_t)c.L;
+    return c.dims == 3 ? L * L * L : L * L;
+}
+
 int validate(const sw_config *c) {
     if (!c) return fail(SW_EINVAL, "config is NULL");
-    if (c->L < 32 || c->L > 32768 || c->L % 32 != 0)
+    if (c->dims != 0 && c->dims != 2 && c->dims != 3) return fail(SW_EINVAL, "dims must be 0, 2 or 3");
+    if (c->dims == 3) {
+        if (!(c->flags & SW_FLAG_LABEL_EQUIV))
+            return fail(SW_EINVAL, "the simple cubic lattice runs on the label-equivalence path (SW_FLAG_LABEL_EQUIV)");
+        if (c->L < 16 || c->L > 1616 || c->L % 16 != 0)
+            return fail(SW_EINVAL, "L of the simple cubic lattice must be a multiple of 16 in [16, 1616]");
+    } else if (c->L < 32 || c->L > 32768 || c->L % 32 != 0) {
         return fail(SW_EINVAL, "L must be a multiple of 32 in [32, 32768]");
+    }
     if (!(c->beta >= 0.0) || !isfinite(c->beta)) return fail(SW_EINVAL, "beta must be finite and >= 0");
     if (!(c->J > 0.0) || !isfinite(c->J)) return fail(SW_EINVAL, "J must be finite and > 0");
     if (c->init != SW_INIT_HOT && c->init != SW_INIT_COLD) return fail(SW_EINVAL, "init must be SW_INIT_HOT or SW_INIT_COLD");
     if (c->tile != 0 && c->tile != 32 && c->tile != 64) return fail(SW_EINVAL, "tile must be 0, 32 or 64");
-    if (c->tile == 64 && c->L % 64 != 0) return fail(SW_EINVAL, "tile 64 needs L to be a multiple of 64");
+    if (c->tile == 64 && c->L % 64 != 0 && c->dims != 3)
+        return fail(SW_EINVAL, "tile 64 needs L to be a multiple of 64");
     if ((c->flags & ~(SW_FLAG_LABELS | SW_FLAG_DENSE_HIST | SW_FLAG_LABEL_EQUIV)) != 0u)
         return fail(SW_EINVAL, "unknown flag bits");
     if (c->ring < 0 || c->ring > (int64_t)1 << 30) return fail(SW_EINVAL, "ring must be in [0, 2^30]");
@@ -80,7 +93,7 @@ int validate(const sw_config *c) {
 }
 
 Layout layout_of(const sw_config &c) {
-    const size_t L = (size_t)c.L, N = L * L;
+    const size_t L = (size_t)c.L, N = sites_of(c);
     const bool le = (c.flags & SW_FLAG_LABEL_EQUIV) != 0u;
     const size_t tw = (size_t)resolve_tile(c);
     // the label-equivalence path keeps no tile structures; its group
@@ -131,6 +144,8 @@ Dev make_dev(const sw_config &c, char *base, const Layout &lo) {
     d.tw = (uint32_t)resolve_tile(c);
     d.ntx = d.L / d.tw;
     d.ntiles = d.ntx * d.ntx;
+    d.dims = c.dims == 3 ? 3u : 2u;
+    d.nsite = sites_of(c);
     d.ngroups = (d.ntiles + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
     // Potts coupling: one J per equal pair, p = 1 - exp(-beta J) (the Ising
     // threshold at half the coupling)
@@ -160,7 +175,8 @@ Dev make_dev(const sw_config &c, char *base, const Layout &lo) {
     d.dense = (c.flags & SW_FLAG_DENSE_HIST) ? (uint64_t *)(base + lo.dense) : nullptr;
     if (le) {
         d.ntiles = 0;
-        d.ngroups = (uint32_t)(((size_t)d.L * d.L + swmi::kLeChunk - 1) / swmi::kLeChunk);
+        d.ntx = 0;
+        d.ngroups = (uint32_t)((d.nsite + swmi::kLeChunk - 1) / swmi::kLeChunk);
         d.le_mask = (uint8_t *)(base + lo.le_mask);
         d.le_cnt = (uint32_t *)(base + lo.le_cnt);
         d.le_rsp = (int8_t *)(base + lo.le_rsp);
@@ -323,7 +339,7 @@ int sw_create_ex(const sw_config *cfg, void *dev_workspace, size_t ws_bytes, voi
     const sw_config &c = s->cfg;
     s->dev = make_dev(c, (char *)s->ws, lo);
     if (c.flags & SW_FLAG_LABEL_EQUIV) {
-        s->dev.le_grid = swmi::le_grid_size();
+        s->dev.le_grid = swmi::le_grid_size(s->dev.dims);
         if (s->dev.le_grid == 0) {
             sw_destroy(s);
             return fail(SW_EHIP, "cannot size the cooperative labelling launch");
@@ -482,7 +498,7 @@ int sw_observables(sw_sim *s, sw_obs *out) {
 int sw_cluster_hist(sw_sim *s, uint64_t *counts, int64_t len) {
     if (!s || !counts) return fail(SW_EINVAL, "sim or counts is NULL");
     if (!s->dev.dense) return fail(SW_ESTATE, "sim was created without SW_FLAG_DENSE_HIST");
-    const int64_t n = (int64_t)s->dev.L * s->dev.L;
+    const int64_t n = (int64_t)s->dev.nsite;
     if (len < n + 1) return fail(SW_ERANGE, "len must be >= N + 1");
     if (s->next_sweep == s->first_valid) return fail(SW_ESTATE, "no sweep has run since the last reset / set_spins");
     int rc = ensure_device(s);
@@ -494,7 +510,7 @@ int sw_cluster_hist(sw_sim *s, uint64_t *counts, int64_t len) {
 
 int sw_get_spins(sw_sim *s, int8_t *host, int64_t n) {
     if (!s || !host) return fail(SW_EINVAL, "sim or host is NULL");
-    if (n != (int64_t)s->dev.L * s->dev.L) return fail(SW_ERANGE, "n must equal L*L");
+    if (n != (int64_t)s->dev.nsite) return fail(SW_ERANGE, "n must equal the number of sites");
     int rc = ensure_device(s);
     if (rc != SW_OK) return rc;
     HIP_TRY(hipMemcpyAsync(host, s->dev.spins[s->next_sweep & 1u], (size_t)n, hipMemcpyDeviceToHost, s->stream));
@@ -504,7 +520,7 @@ int sw_get_spins(sw_sim *s, int8_t *host, int64_t n) {
 
 int sw_set_spins(sw_sim *s, const int8_t *host, int64_t n, uint64_t next_sweep) {
     if (!s || !host) return fail(SW_EINVAL, "sim or host is NULL");
-    if (n != (int64_t)s->dev.L * s->dev.L) return fail(SW_ERANGE, "n must equal L*L");
+    if (n != (int64_t)s->dev.nsite) return fail(SW_ERANGE, "n must equal the number of sites");
     const int32_t q = s->cfg.q;
     for (int64_t i = 0; i < n; ++i) {
         if (q == 0 && host[i] != 1 && host[i] != -1) return fail(SW_EINVAL, "spins must be +1 or -1");
@@ -520,7 +536,7 @@ int sw_set_spins(sw_sim *s, const int8_t *host, int64_t n, uint64_t next_sweep) 
 int sw_get_labels(sw_sim *s, uint32_t *host, int64_t n) {
     if (!s || !host) return fail(SW_EINVAL, "sim or host is NULL");
     if (!s->dev.labels) return fail(SW_ESTATE, "sim was created without SW_FLAG_LABELS");
-    if (n != (int64_t)s->dev.L * s->dev.L) return fail(SW_ERANGE, "n must equal L*L");
+    if (n != (int64_t)s->dev.nsite) return fail(SW_ERANGE, "n must equal the number of sites");
     if (s->next_sweep == s->first_valid) return fail(SW_ESTATE, "no sweep has run since the last reset / set_spins");
     int rc = ensure_device(s);
     if (rc != SW_OK) return rc;
@@ -541,7 +557,8 @@ int32_t sw_label_passes(sw_sim *s) {
 uint32_t sw_threshold(const sw_sim *s) { return s ? s->dev.T : 0u; }
 int64_t sw_next_sweep(const sw_sim *s) { return s ? (int64_t)s->next_sweep : -1; }
 int32_t sw_lattice(const sw_sim *s) { return s ? (int32_t)s->dev.L : 0; }
-int32_t sw_tile(const sw_sim *s) { return s ? (int32_t)s->dev.tw : 0; }
+int32_t sw_tile(const sw_sim *s) { return s ? (s->dev.le_grid ? 0 : (int32_t)s->dev.tw) : 0; }
+int64_t sw_sites(const sw_sim *s) { return s ? (int64_t)s->dev.nsite : -1; }
 
 void sw_destroy(sw_sim *s) {
     if (!s) return;

@@ -70,6 +70,8 @@ struct Dev {
     uint32_t ring_cap;
     uint32_t le_grid;     // workgroups of the cooperative labelling kernel (0: tile path)
     uint32_t q;           // 0: Ising; 2..kMaxQ: q-state Potts (label-equivalence path)
+    uint32_t dims;        // 2: L x L; 3: L x L x L (label-equivalence path)
+    uint64_t nsite;       // N = L^dims
     double J;
 };
 
@@ -102,7 +104,7 @@ struct BatchDev {
 // Label-equivalence path: stages 0..4 of a sweep (bonds, iterated labelling,
 // new spins and sizes, statistics, record), and the cooperative grid size.
 hipError_t launch_le_stage(const Dev &d, int stage, hipStream_t s);
-uint32_t le_grid_size();
+uint32_t le_grid_size(uint32_t dims);
 constexpr uint32_t kLeChunk = 4096;  // sites per workgroup in the per-site passes
 enum { LE_PASSES = 3, LE_STATUS = 4 };
 

@@ -1223,7 +1223,7 @@ __global__ __launch_bounds__(TW *TW / 16) void k_resolve_b(const Dev *devs, cons
 // cold = all +1; for the Potts model hot = floor(w q / 2^32) of that word,
 // cold = all 0.  16 sites per thread.
 __global__ __launch_bounds__(256) void k_init(Dev d, int cold) {
-    const size_t n16 = (size_t)d.L * d.L / 16u;
+    const size_t n16 = d.nsite / 16u;
     const uint32_t pc = (uint32_t)(*d.tdev & 1u);
     int8_t *sp = d.spins[pc];
     const uint32_t fill = d.q ? 0u : 0x01010101u;
@@ -1258,13 +1258,13 @@ inline uint32_t grid_for(size_t n, uint32_t per_block, uint32_t cap) {
 }  // namespace
 
 hipError_t launch_init(const Dev &d, int cold, hipStream_t s) {
-    const size_t n16 = (size_t)d.L * d.L / 16u;
+    const size_t n16 = d.nsite / 16u;
     k_init<<<grid_for(n16, 256, 65536), 256, 0, s>>>(d, cold);
     return hipGetLastError();
 }
 
 hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
-    const size_t n = (size_t)d.L * d.L;
+    const size_t n = d.nsite;
     if (d.le_grid) {  // label-equivalence path
         if (stage == 0 && d.dense) k_zero_u64<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(d.dense, n + 1);
         if (stage != 4) {

@@ -52,15 +52,40 @@ __global__ __launch_bounds__(256) void k_le_bond(Dev d) {
     }
 }
 
+// Bonds of the simple cubic lattice to +x, +y and +z: one Philox call per
+// site, words 0, 1, 2 of counter {s, t, 4, 0}.
+__global__ __launch_bounds__(256) void k_le_bond3(Dev d) {
+    const uint32_t L = d.L, LL = L * L;
+    const uint32_t N = (uint32_t)d.nsite;
+    const uint32_t t = (uint32_t)*d.tdev;
+    const int8_t *sp = d.spins[0];
+    // N <= 1616^3, so s + the grid stride stays below 2^32
+    for (uint32_t s = blockIdx.x * 256u + threadIdx.x; s < N; s += gridDim.x * 256u) {
+        const uint32_t x = s % L, yz = s / L, y = yz % L, z = yz / L;
+        const int8_t a = sp[s];
+        const int8_t e = sp[x + 1u == L ? s - x : s + 1u];
+        const int8_t n = sp[y + 1u == L ? s - y * L : s + L];
+        const int8_t u = sp[z + 1u == L ? s - z * LL : s + LL];
+        uint32_t w0 = s, w1 = t, w2 = 4u, w3 = 0u;
+        philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
+        const uint32_t T = d.T;
+        d.le_mask[s] = (uint8_t)((uint32_t)(a == e && w0 < T) | ((uint32_t)(a == n && w1 < T) << 1) |
+                                 ((uint32_t)(a == u && w2 < T) << 2));
+    }
+}
+
 // All labelling passes in one cooperative launch.  Flags rotate over three
 // words: pass k raises flag k mod 3, every thread reads it after the pass's
 // last barrier, and flag (k+1) mod 3 is cleared at the start of pass k --
 // its last readers finished with pass k-2.  Every thread therefore takes
 // the same exit decision, and the pass cap bounds the loop.
+// DIMS = 3: the scan looks at the six neighbours of the simple cubic lattice
+// (bit 2 of a site's mask is its bond to +z).
+template <int DIMS>
 __global__ __launch_bounds__(256) void k_le_label(Dev d) {
     cg::grid_group g = cg::this_grid();
     const uint32_t L = d.L;
-    const size_t N = (size_t)L * L;
+    const size_t N = d.nsite;
     const size_t gid = blockIdx.x * (size_t)256 + threadIdx.x, stride = (size_t)gridDim.x * 256;
     uint32_t *lab = d.labels;
     const uint8_t *mk = d.le_mask;
@@ -79,18 +104,33 @@ __global__ __launch_bounds__(256) void k_le_label(Dev d) {
         // scan: the entry of my label points at the smallest bonded label
         bool changed = false;
         for (size_t i = gid; i < N; i += stride) {
-            const uint32_t y = (uint32_t)(i / L), x = (uint32_t)(i % L);
-            const size_t row = (size_t)y * L;
-            const size_t e = row + (x + 1u == L ? 0u : x + 1u), w = row + (x == 0u ? L - 1u : x - 1u);
-            const size_t n = (size_t)(y + 1u == L ? 0u : y + 1u) * L + x;
-            const size_t s = (size_t)(y == 0u ? L - 1u : y - 1u) * L + x;
-            const uint32_t bm = mk[i], bw = mk[w], bs = mk[s];
             const uint32_t l = ld(&lab[i]);
             uint32_t m = l;
-            if (bm & 1u) m = min(m, ld(&lab[e]));
-            if (bm & 2u) m = min(m, ld(&lab[n]));
-            if (bw & 1u) m = min(m, ld(&lab[w]));
-            if (bs & 2u) m = min(m, ld(&lab[s]));
+            if (DIMS == 2) {
+                const uint32_t y = (uint32_t)(i / L), x = (uint32_t)(i % L);
+                const size_t row = (size_t)y * L;
+                const size_t e = row + (x + 1u == L ? 0u : x + 1u), w = row + (x == 0u ? L - 1u : x - 1u);
+                const size_t n = (size_t)(y + 1u == L ? 0u : y + 1u) * L + x;
+                const size_t s = (size_t)(y == 0u ? L - 1u : y - 1u) * L + x;
+                const uint32_t bm = mk[i], bw = mk[w], bs = mk[s];
+                if (bm & 1u) m = min(m, ld(&lab[e]));
+                if (bm & 2u) m = min(m, ld(&lab[n]));
+                if (bw & 1u) m = min(m, ld(&lab[w]));
+                if (bs & 2u) m = min(m, ld(&lab[s]));
+            } else {
+                const uint32_t si = (uint32_t)i, LL = L * L;
+                const uint32_t x = si % L, yz = si / L, y = yz % L, z = yz / L;
+                const uint32_t e = x + 1u == L ? si - x : si + 1u, w = x == 0u ? si + (L - 1u) : si - 1u;
+                const uint32_t n = y + 1u == L ? si - y * L : si + L, s = y == 0u ? si + (L - 1u) * L : si - L;
+                const uint32_t u = z + 1u == L ? si - z * LL : si + LL, dn = z == 0u ? si + (L - 1u) * LL : si - LL;
+                const uint32_t bm = mk[si], bw = mk[w], bs = mk[s], bd = mk[dn];
+                if (bm & 1u) m = min(m, ld(&lab[e]));
+                if (bm & 2u) m = min(m, ld(&lab[n]));
+                if (bm & 4u) m = min(m, ld(&lab[u]));
+                if (bw & 1u) m = min(m, ld(&lab[w]));
+                if (bs & 2u) m = min(m, ld(&lab[s]));
+                if (bd & 4u) m = min(m, ld(&lab[dn]));
+            }
             if (m < l) {
                 atomicMin(&lab[l], m);
                 changed = true;
@@ -123,7 +163,7 @@ __global__ __launch_bounds__(256) void k_le_label(Dev d) {
 // Ising model a wavefront's 64 sites lie in one 128-site block, so the
 // Philox call of the cluster-spin rule is the same for all its lanes.
 __global__ __launch_bounds__(256) void k_le_roots(Dev d) {
-    const size_t N = (size_t)d.L * d.L;
+    const size_t N = d.nsite;
     const uint32_t t = (uint32_t)*d.tdev;
     for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < N; i += (size_t)gridDim.x * 256) {
         if (d.labels[i] != (uint32_t)i) continue;
@@ -144,7 +184,7 @@ __global__ __launch_bounds__(256) void k_le_flip(Dev d) {
         hv[i] = 0u;
     }
     __syncthreads();
-    const size_t N = (size_t)d.L * d.L;
+    const size_t N = d.nsite;
     const size_t b0 = (size_t)blockIdx.x * kLeChunk, b1 = min(b0 + kLeChunk, N);
     int8_t *sp = d.spins[0];
     for (size_t i = b0 + threadIdx.x; i < b1; i += 256u) {
@@ -178,24 +218,34 @@ __global__ __launch_bounds__(256) void k_le_stats(Dev d) {
     for (uint32_t i = threadIdx.x; i < (uint32_t)GP_END; i += 256u) s_acc[i] = 0ull;
     __syncthreads();
     const uint32_t L = d.L;
-    const size_t N = (size_t)L * L;
+    const size_t N = d.nsite;
     const size_t b0 = (size_t)blockIdx.x * kLeChunk, b1 = min(b0 + kLeChunk, N);
     const int8_t *sp = d.spins[0];
+    const bool cubic = d.dims == 3u;
     int64_t e = 0, m = 0;
     uint64_t n = 0, mx = 0, sq = 0;
     __shared__ unsigned int s_cnt[kMaxQ];
     if (threadIdx.x < (uint32_t)kMaxQ) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
     for (size_t i = b0 + threadIdx.x; i < b1; i += 256u) {
-        const uint32_t y = (uint32_t)(i / L), x = (uint32_t)(i % L);
         const int32_t si = sp[i];
-        const int32_t se = sp[(size_t)y * L + (x + 1u == L ? 0u : x + 1u)];
-        const int32_t sn = sp[(size_t)(y + 1u == L ? 0u : y + 1u) * L + x];
+        int32_t se, sn, su = 0;
+        if (cubic) {  // +x, +y, +z neighbours of site (z L + y) L + x
+            const uint32_t s = (uint32_t)i, LL = L * L;
+            const uint32_t x = s % L, yz = s / L, y = yz % L, z = yz / L;
+            se = sp[x + 1u == L ? s - x : s + 1u];
+            sn = sp[y + 1u == L ? s - y * L : s + L];
+            su = sp[z + 1u == L ? s - z * LL : s + LL];
+        } else {
+            const uint32_t y = (uint32_t)(i / L), x = (uint32_t)(i % L);
+            se = sp[(size_t)y * L + (x + 1u == L ? 0u : x + 1u)];
+            sn = sp[(size_t)(y + 1u == L ? 0u : y + 1u) * L + x];
+        }
         if (d.q) {  // Potts: equal pairs and value populations
-            e += (si == se) + (si == sn);
+            e += (si == se) + (si == sn) + (cubic && si == su);
             atomicAdd(&s_cnt[(uint32_t)si < (uint32_t)kMaxQ ? si : 0], 1u);
         } else {
-            e += si * se + si * sn;
+            e += si * se + si * sn + si * su;
             m += si;
         }
         if (d.labels[i] == (uint32_t)i) {
@@ -236,25 +286,32 @@ inline uint32_t grid_cap(size_t n, uint32_t per, uint32_t cap) {
 
 }  // namespace
 
-uint32_t le_grid_size() {
+uint32_t le_grid_size(uint32_t dims) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_le_label, 256, 0) != hipSuccess) return 0;
+    const hipError_t e = dims == 3u ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_le_label<3>, 256, 0)
+                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_le_label<2>, 256, 0);
+    if (e != hipSuccess) return 0;
     return (uint32_t)(cus * (per < 1 ? 1 : per));
 }
 
 hipError_t launch_le_stage(const Dev &d, int stage, hipStream_t s) {
-    const size_t N = (size_t)d.L * d.L;
+    const size_t N = d.nsite;
+    const bool cubic = d.dims == 3u;
     switch (stage) {
     case 0:
-        k_le_bond<<<grid_cap(N / 2, 256, 65536), 256, 0, s>>>(d);
+        if (cubic)
+            k_le_bond3<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);
+        else
+            k_le_bond<<<grid_cap(N / 2, 256, 65536), 256, 0, s>>>(d);
         break;
     case 1: {
         Dev dd = d;
         void *args[] = {&dd};
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_le_label), dim3(d.le_grid), dim3(256),
-                                          args, 0, s);
+        const void *fn = cubic ? reinterpret_cast<const void *>(k_le_label<3>)
+                               : reinterpret_cast<const void *>(k_le_label<2>);
+        return hipLaunchCooperativeKernel(fn, dim3(d.le_grid), dim3(256), args, 0, s);
     }
     case 2:
         k_le_roots<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);

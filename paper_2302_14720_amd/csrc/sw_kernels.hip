@@ -821,25 +821,30 @@ __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group)
     uint32_t *par = d.parent[pc];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t g0 = group * (uint32_t)kGroupTiles;
-    // wavefront wv owns tiles g0 + wv + 4q (q < TPW), i.e. TPW x kNodeSlots
-    // slots; each lane chases the roots of up to 8 slots at once, one level
-    // per round, so their loads overlap
-    constexpr uint32_t TPW = kGroupTiles / 4;
-    uint32_t nkq[TPW];
+    // wavefront wv owns tiles g0 + wv + 4q (q < 4); their nodes are numbered
+    // one after the other (about 80 per tile at beta_c, so mostly one batch),
+    // and each lane chases the roots of up to 8 nodes at once, one level per
+    // round, so their loads overlap
+    static_assert(kGroupTiles == 16, "four tiles per wavefront");
+    uint32_t nkq[4];
 #pragma unroll
-    for (uint32_t q = 0; q < TPW; ++q) {
+    for (uint32_t q = 0; q < 4u; ++q) {
         const uint32_t tile = g0 + wv + 4u * q;
         const uint32_t v = d.nk[pc][min(tile, d.ntiles - 1u)];  // issued unconditionally
         nkq[q] = tile < d.ntiles ? min(v, 252u) : 0u;
     }
+    const uint32_t pre1 = nkq[0], pre2 = pre1 + nkq[1], pre3 = pre2 + nkq[2], tot = pre3 + nkq[3];
     constexpr uint32_t kChase = 8;
 #pragma unroll
-    for (uint32_t m0 = 0; m0 < TPW * kNodeSlots / 64u; m0 += kChase) {
+    for (uint32_t m0 = 0; m0 < 4u * 252u / 64u + 1u; m0 += kChase) {
+        if (64u * m0 >= tot) break;
         uint32_t nd[kChase], r[kChase];
 #pragma unroll
         for (uint32_t j = 0; j < kChase; ++j) {
-            const uint32_t slot = lane + 64u * (m0 + j), q = slot / kNodeSlots, k = slot % kNodeSlots;
-            nd[j] = k < nkq[q] ? (g0 + wv + 4u * q) * kNodeSlots + k : kEmpty;
+            const uint32_t i = lane + 64u * (m0 + j);
+            const uint32_t q = (uint32_t)(i >= pre1) + (uint32_t)(i >= pre2) + (uint32_t)(i >= pre3);
+            const uint32_t base = q == 0u ? 0u : q == 1u ? pre1 : q == 2u ? pre2 : pre3;
+            nd[j] = i < tot ? (g0 + wv + 4u * q) * kNodeSlots + (i - base) : kEmpty;
             r[j] = nd[j];
         }
         bool more = true;
@@ -915,12 +920,20 @@ __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
     const uint32_t g0 = group * (uint32_t)kGroupTiles;
     uint64_t n = 0, mx = 0, sq = 0;
     int64_t e = 0, m = 0;
-    for (uint32_t tt = wv; tt < (uint32_t)kGroupTiles; tt += 4u) {
-        const uint32_t tile = g0 + tt;
-        if (tile >= d.ntiles) break;
-        const uint32_t K = min(d.nk[pc][tile], 252u);
-        for (uint32_t k = lane; k < K; k += 64u) {
-            const uint32_t node = tile * kNodeSlots + k;
+    // the nodes of the wavefront's four tiles g0 + wv + 4q, one after the other
+    uint32_t nkq[4];
+#pragma unroll
+    for (uint32_t q = 0; q < 4u; ++q) {
+        const uint32_t tile = g0 + wv + 4u * q;
+        const uint32_t v = d.nk[pc][min(tile, d.ntiles - 1u)];
+        nkq[q] = tile < d.ntiles ? min(v, 252u) : 0u;
+    }
+    const uint32_t pre1 = nkq[0], pre2 = pre1 + nkq[1], pre3 = pre2 + nkq[2], tot = pre3 + nkq[3];
+    {
+        for (uint32_t i = lane; i < tot; i += 64u) {
+            const uint32_t q = (uint32_t)(i >= pre1) + (uint32_t)(i >= pre2) + (uint32_t)(i >= pre3);
+            const uint32_t base = q == 0u ? 0u : q == 1u ? pre1 : q == 2u ? pre2 : pre3;
+            const uint32_t node = (g0 + wv + 4u * q) * kNodeSlots + (i - base);
             if (par[node] == node) {
                 const uint32_t S = d.nsize[node];
                 d.rspin[node] = cluster_spin(d.key[node], t, d.seed_lo, d.seed_hi);

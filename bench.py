@@ -145,6 +145,31 @@ def batched_vs_plain(args):
     }
 
 
+def potts_tile(args):
+    """The q = 3 Potts model on the tile path (32-wide tiles) at its critical
+    point ln(1 + sqrt 3), headline lattice, hot start; per-kernel times from
+    the measurement entry point."""
+    import paper_2302_14720_amd as sw
+
+    q, L = 3, args.L
+    beta_q = math.log(1.0 + math.sqrt(q))
+    s = sw.Sim(L, beta_q, 1.0, 11, q=q)
+    s.sweep(10)
+    s.sync()
+    t0 = time.perf_counter()
+    s.sweep(args.potts_steps)
+    s.sync()
+    dt = time.perf_counter() - t0
+    prof = s.profile(5)
+    s.close()
+    out = {"workload": f"2D q=3 Potts, L={L} periodic, J=1, beta=ln(1+sqrt 3), hot start seed 11, tile path (32-wide tiles)",
+           "value": L * L * args.potts_steps / dt, "unit": "site-updates/s", "sweeps": args.potts_steps,
+           "ms_per_step": dt * 1e3 / args.potts_steps, "kernel_ms": prof}
+    print(f"[bench] Potts q=3 tile path L={L}: {out['value']:.4g} site-updates/s, kernel ms {prof}",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def serving(args):
     """Continuous batching: jobs arrive as a Poisson process (L log-uniform in
     [128, 4096] rounded to 32, beta uniform in [0.35, 0.55], sweeps uniform in
@@ -280,6 +305,8 @@ def main() -> int:
                     help="timed sweeps of the label-equivalence comparison, its Potts and its "
                          "simple cubic runs (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the serving leg, jobs/s")
+    ap.add_argument("--potts-steps", type=int, default=50,
+                    help="timed sweeps of the q = 3 Potts model on the tile path (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for "
                          "HBM byte counters)")
@@ -405,6 +432,7 @@ def main() -> int:
                        "first_sweep_max_cluster": int(crec["max_cluster"])},
         "batched": None if args.no_batched else batched_vs_plain(args),
         "serving": serving(args) if args.serve_jobs > 0 else None,
+        "potts_tile": potts_tile(args) if args.potts_steps > 0 else None,
         "label_equivalence": label_equivalence(args, value) if args.le_steps > 0 else None,
     }
     if not args.no_cpu_baseline:

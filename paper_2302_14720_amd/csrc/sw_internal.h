@@ -38,7 +38,8 @@ constexpr int kGroupTiles = 16;       // tiles per workgroup in k_flatten / k_ro
 constexpr uint32_t kUG = 4;           // side, in tiles, of a k_ulocal group
 
 // tile partial (int32 words)
-enum { TP_E = 0, TP_M = 1, TP_N = 2, TP_MAX = 3, TP_SQ = 4, TP_HIST = 5 };  // hist: 12 bins
+// hist: 12 bins; TP_CNT..: population of each Potts value
+enum { TP_E = 0, TP_M = 1, TP_N = 2, TP_MAX = 3, TP_SQ = 4, TP_HIST = 5, TP_CNT = 17 };
 // group partial / accumulator (uint64 words)
 // GP_CNT..: population of each Potts value
 enum { GP_N = 0, GP_MAX = 1, GP_SQ = 2, GP_E = 3, GP_M = 4, GP_HIST = 5, GP_CNT = 38, GP_END = 46 };

@@ -177,7 +177,12 @@ __device__ __forceinline__ uint32_t byte_at(const uint4 &v, int q) {
 // of this tile's previous output to its spin as an up bit (1 for +1): final
 // spins 0x01 / 0xFF map to themselves, node code 2 + k to the spin of node
 // k's root.
-template <int TW>
+// Potts model on the tile path (32-wide tiles, so at most 124 nodes per
+// tile): a byte below kPottsCode is a final value 0..7, kPottsCode + k
+// refers to node k of its tile.
+constexpr uint32_t kPottsCode = 8;
+
+template <int TW, bool POTTS>
 __device__ __forceinline__ void load_table(const Dev &d, uint32_t tile, uint32_t pp, uint8_t *s_tab,
                                            uint32_t tid) {
     constexpr int NT = TW * TW / 16;
@@ -185,12 +190,19 @@ __device__ __forceinline__ void load_table(const Dev &d, uint32_t tile, uint32_t
     const uint32_t kprev = min(d.nk[pp][tile], 252u);
     const uint32_t *par_prev = d.parent[pp];
     for (uint32_t b = tid; b < 256u; b += NT) {
-        uint8_t val = b == 0xFFu ? 0u : 1u;
-        const uint32_t k = b - 2u;
+        uint8_t val;
+        uint32_t k;
+        if constexpr (POTTS) {
+            val = (uint8_t)(b & 7u);
+            k = b - kPottsCode;
+        } else {
+            val = b == 0xFFu ? 0u : 1u;
+            k = b - 2u;
+        }
         if (k < kprev) {
             uint32_t p = par_prev[tile * kNodeSlots + k];
             p = p < nnodes ? p : 0u;
-            val = d.rspin[p] > 0 ? 1u : 0u;
+            val = POTTS ? (uint8_t)((uint32_t)d.rspin[p] & 7u) : (d.rspin[p] > 0 ? 1u : 0u);
         }
         s_tab[b] = val;
     }
@@ -213,6 +225,60 @@ __device__ __forceinline__ uint32_t decode16_remote(const uint4 &v, uint32_t til
     return up;
 }
 
+// Potts value (0..7) of a byte of tile `tile`'s previous output.
+__device__ __forceinline__ uint32_t potts_byte(uint32_t b, uint32_t tile, const uint32_t *par_prev,
+                                               const int8_t *rspin, uint32_t nnodes) {
+    const uint32_t k = b - kPottsCode;
+    if (k < 252u) {
+        uint32_t p = par_prev[tile * kNodeSlots + k];
+        p = p < nnodes ? p : 0u;
+        return (uint32_t)rspin[p] & 7u;
+    }
+    return b & 7u;
+}
+
+// Values of 16 sites as three bit planes (bit q of pl[i] = bit i of site q).
+__device__ __forceinline__ void decode16_potts(const uint4 &v, const uint8_t *s_tab, uint32_t pl[3]) {
+    pl[0] = pl[1] = pl[2] = 0u;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t x = s_tab[byte_at(v, q)];
+        pl[0] |= (x & 1u) << q;
+        pl[1] |= ((x >> 1) & 1u) << q;
+        pl[2] |= (x >> 2) << q;
+    }
+}
+
+__device__ __forceinline__ void decode16_potts_remote(const uint4 &v, uint32_t tile, const uint32_t *par_prev,
+                                                      const int8_t *rspin, uint32_t nnodes, uint32_t pl[3]) {
+    pl[0] = pl[1] = pl[2] = 0u;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t x = potts_byte(byte_at(v, q), tile, par_prev, rspin, nnodes);
+        pl[0] |= (x & 1u) << q;
+        pl[1] |= ((x >> 1) & 1u) << q;
+        pl[2] |= (x >> 2) << q;
+    }
+}
+
+// Equal-neighbour masks of 16 sites from their bit planes and those of the
+// E and N neighbours; equal pairs and the population of every value 0..7
+// (two 16-bit counts per word).
+__device__ __forceinline__ void potts_counts(const uint32_t pl[3], uint32_t cpk[4]) {
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+        uint32_t c[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int v = k + h;
+            const uint32_t m = ~((pl[0] ^ ((v & 1) ? 0xFFFFu : 0u)) | (pl[1] ^ ((v & 2) ? 0xFFFFu : 0u)) |
+                                 (pl[2] ^ ((v & 4) ? 0xFFFFu : 0u))) & 0xFFFFu;
+            c[h] = (uint32_t)__popc(m);
+        }
+        cpk[k >> 1] = c[0] | (c[1] << 16);
+    }
+}
+
 // =====================================================================
 // k_tile: bonds (Sec. 2.1), tile-local clusters (Sec. 2.3), new spins of
 // tile-interior clusters (Sec. 2.4), measurement of the incoming
@@ -224,7 +290,11 @@ __device__ __forceinline__ uint32_t decode16_remote(const uint4 &v, uint32_t til
 // unions of run starts; each run start is then pointed at its root, which
 // collects the cluster size and, after numbering, the output byte.
 // =====================================================================
-template <int TW>
+// POTTS: the q-state Potts model (32-wide tiles): spins are values 0..7
+// held as three bit planes, bonds join equal values, an interior cluster
+// takes the Potts value of its root site, node codes start at kPottsCode,
+// and the tile measures equal pairs and the population of every value.
+template <int TW, bool POTTS = false>
 __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     using Row = typename RowOf<TW>::T;
     constexpr int NT = TW * TW / 16;
@@ -232,6 +302,10 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     constexpr int NS = TW * TW;
     constexpr int NW = NS / 32;
     constexpr int NWAVE = (NT + 63) / 64;
+    constexpr int NPL = POTTS ? 3 : 1;  // bit planes of a spin
+    constexpr uint32_t EW = (TW + 31) / 32;
+    constexpr uint32_t CB = POTTS ? kPottsCode : 2u;  // output byte of node 0
+    static_assert(!POTTS || TW == 32, "the Potts tile path uses 32-wide tiles");
 
     // One word per site, rows padded to PS = TW + 1 words so that the 16
     // sites a lane gathers at equal offsets fall in distinct banks.  Low 16
@@ -240,14 +314,14 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     // the root's output byte.
     constexpr uint32_t PS = TW + 1;
     __shared__ uint32_t s_par[TW * PS];
-    __shared__ Row s_up[TW + 1];
+    __shared__ Row s_up[NPL * (TW + 1)];
     __shared__ Row s_ebnb[2 * TW];  // bond masks to E (rows 0..TW-1) and N (rows TW..2TW-1)
     Row *const s_eb = s_ebnb;
     Row *const s_nb = s_ebnb + TW;
     __shared__ Row s_fb[TW];
     __shared__ Row s_xn;
-    __shared__ uint32_t s_eup[(TW + 31) / 32];
-    __shared__ uint32_t s_xe[(TW + 31) / 32];
+    __shared__ uint32_t s_eup[NPL * EW];
+    __shared__ uint32_t s_xe[EW];
     __shared__ uint32_t s_bf[NW];
     __shared__ uint32_t s_pf[NW];
     __shared__ uint8_t s_tab[256];
@@ -256,7 +330,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     // masks, which are dead once the unions are done
     __shared__ uint32_t s_node_own[TW == 64 ? 1 : 4 * TW];
     uint32_t *const s_node = TW == 64 ? reinterpret_cast<uint32_t *>(s_ebnb) : s_node_own;
-    __shared__ int32_t s_red[NWAVE][4];
+    __shared__ int32_t s_red[NWAVE][POTTS ? 8 : 4];
     __shared__ uint32_t s_k;
 
     const uint32_t tid = threadIdx.x;
@@ -291,10 +365,25 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         const uint32_t gxe = (gx0 + 16u == L) ? 0u : gx0 + 16u;
         ve = (uint8_t)sin[(size_t)gy * L + gxe];
     }
-    load_table<TW>(d, tile, pp, s_tab, tid);
+    load_table<TW, POTTS>(d, tile, pp, s_tab, tid);
 
-    // flip bits of every tile row: one Philox call per row of TW sites
-    if (tid < (uint32_t)TW) {
+    // Potts: the value each of this lane's 16 sites would give its cluster
+    // as its root (4 bits per site): word i of the output for counter
+    // {s >> 2, t, 3, 0} for site s = 4j + i past the lane's first site
+    uint64_t pv = 0;
+    if constexpr (POTTS) {
+        const uint32_t r0 = gy * L + gx0, q = d.q;
+#pragma unroll
+        for (uint32_t j = 0; j < 4u; ++j) {
+            uint32_t w0 = (r0 >> 2) + j, w1 = t, w2 = 3u, w3 = 0u;
+            philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
+            const uint64_t v4 = (uint64_t)(((uint64_t)w0 * q) >> 32) | ((((uint64_t)w1 * q) >> 32) << 4) |
+                                ((((uint64_t)w2 * q) >> 32) << 8) | ((((uint64_t)w3 * q) >> 32) << 12);
+            pv |= v4 << (16u * j);
+        }
+    }
+    // Ising: flip bits of every tile row, one Philox call per row of TW sites
+    if (!POTTS && tid < (uint32_t)TW) {
         const uint32_t r0 = (ty * TW + tid) * L + tx * TW;
         uint32_t w0 = r0 >> 7, w1 = t, w2 = 1u, w3 = 0u;
         philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
@@ -307,38 +396,79 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         }
     }
     for (uint32_t i = tid; i < (uint32_t)NW; i += NT) s_bf[i] = 0u;
-    if (tid < (uint32_t)((TW + 31) / 32)) {
-        s_eup[tid] = 0u;
-        s_xe[tid] = 0u;
-    }
+    if (tid < EW) s_xe[tid] = 0u;
+    if (tid < NPL * EW) s_eup[tid] = 0u;
     if (tid < 12u) s_hist[tid] = 0u;
     if (tid == 0) s_xn = 0;
     __syncthreads();
 
-    // ---- decode the incoming configuration to up-spin masks
-    const uint32_t up = decode16<TW>(v, s_tab);
-    reinterpret_cast<uint16_t *>(s_up)[ly * RPT + seg] = (uint16_t)up;
-    if (ly == TW - 1) {
-        const uint32_t upn = decode16_remote(vn, north, par_prev, d.rspin, nnodes);
-        reinterpret_cast<uint16_t *>(s_up)[TW * RPT + seg] = (uint16_t)upn;
-    }
-    if (seg == RPT - 1) {
-        if (resolve_byte(ve, east, par_prev, d.rspin, nnodes) > 0) atomicOr(&s_eup[ly >> 5], 1u << (ly & 31u));
+    // ---- decode the incoming configuration to up-spin masks (Potts: bit
+    // planes of the values)
+    uint32_t up = 0u, pl[3] = {0u, 0u, 0u};
+    if constexpr (POTTS) {
+        decode16_potts(v, s_tab, pl);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[ly * RPT + seg] = (uint16_t)pl[b];
+        if (ly == TW - 1) {
+            uint32_t pn[3];
+            decode16_potts_remote(vn, north, par_prev, d.rspin, nnodes, pn);
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[TW * RPT + seg] = (uint16_t)pn[b];
+        }
+        if (seg == RPT - 1) {
+            const uint32_t ev = potts_byte(ve, east, par_prev, d.rspin, nnodes);
+#pragma unroll
+            for (uint32_t b = 0; b < 3u; ++b)
+                if ((ev >> b) & 1u) atomicOr(&s_eup[b * EW + (ly >> 5)], 1u << (ly & 31u));
+        }
+    } else {
+        up = decode16<TW>(v, s_tab);
+        reinterpret_cast<uint16_t *>(s_up)[ly * RPT + seg] = (uint16_t)up;
+        if (ly == TW - 1) {
+            const uint32_t upn = decode16_remote(vn, north, par_prev, d.rspin, nnodes);
+            reinterpret_cast<uint16_t *>(s_up)[TW * RPT + seg] = (uint16_t)upn;
+        }
+        if (seg == RPT - 1) {
+            if (resolve_byte(ve, east, par_prev, d.rspin, nnodes) > 0) atomicOr(&s_eup[ly >> 5], 1u << (ly & 31u));
+        }
     }
     __syncthreads();
 
     // ---- bonds (Sec. 2.1) and energy / magnetisation of the incoming spins
+    // (Potts: equal pairs and value populations)
     int32_t e_part, m_part;
+    uint32_t cpk[4] = {0u, 0u, 0u, 0u};
     {
-        const Row rowv = s_up[ly];
-        const uint32_t upN = (uint32_t)(s_up[ly + 1] >> x0) & 0xFFFFu;
-        const uint32_t ebit = (s_eup[ly >> 5] >> (ly & 31u)) & 1u;
-        const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
-        const uint32_t upE = (up >> 1) | (nxt << 15);
-        const uint32_t eqE = ~(up ^ upE) & 0xFFFFu;
-        const uint32_t eqN = ~(up ^ upN) & 0xFFFFu;
-        e_part = 2 * (__popc(eqE) + __popc(eqN)) - 32;
-        m_part = 2 * __popc(up) - 16;
+        uint32_t eqE, eqN;
+        if constexpr (POTTS) {
+            uint32_t dE = 0u, dN = 0u;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const Row rowv = s_up[b * (TW + 1) + ly];
+                const uint32_t pN = (uint32_t)(s_up[b * (TW + 1) + ly + 1] >> x0) & 0xFFFFu;
+                const uint32_t ebit = (s_eup[b * EW + (ly >> 5)] >> (ly & 31u)) & 1u;
+                const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
+                const uint32_t pE = (pl[b] >> 1) | (nxt << 15);
+                dE |= pl[b] ^ pE;
+                dN |= pl[b] ^ pN;
+            }
+            eqE = ~dE & 0xFFFFu;
+            eqN = ~dN & 0xFFFFu;
+            e_part = __popc(eqE) + __popc(eqN);
+            m_part = 0;
+            potts_counts(pl, cpk);
+        } else {
+            const Row rowv = s_up[ly];
+            const uint32_t upN = (uint32_t)(s_up[ly + 1] >> x0) & 0xFFFFu;
+            const uint32_t ebit = (s_eup[ly >> 5] >> (ly & 31u)) & 1u;
+            const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
+            const uint32_t upE = (up >> 1) | (nxt << 15);
+            eqE = ~(up ^ upE) & 0xFFFFu;
+            eqN = ~(up ^ upN) & 0xFFFFu;
+            e_part = 2 * (__popc(eqE) + __popc(eqN)) - 32;
+            m_part = 2 * __popc(up) - 16;
+        }
         uint32_t rE = 0u, rN = 0u;
         const uint32_t c0 = (gy * L + gx0) >> 1;
         const uint32_t T = d.T;
@@ -501,7 +631,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         const uint32_t bsh = sbase & 31u;
         const uint32_t bmask = (bfw >> bsh) & 0xFFFFu;
         const uint32_t kbase = s_pf[sbase >> 5] + __popc(bfw & ((1u << bsh) - 1u));
-        const uint32_t fl = (uint32_t)(s_fb[ly] >> x0) & 0xFFFFu;
+        const uint32_t fl = POTTS ? 0u : (uint32_t)(s_fb[ly] >> x0) & 0xFFFFu;
         while (rootmask) {
             const uint32_t q = (uint32_t)__ffs((int)rootmask) - 1u;
             rootmask &= rootmask - 1u;
@@ -511,9 +641,12 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
             if ((bmask >> q) & 1u) {
                 const uint32_t k = kbase + __popc(bmask & ((1u << q) - 1u));
                 s_node[k] = (sbase + q) | (S << 16);
-                code = 2u + k;
+                code = CB + k;
             } else {
-                code = ((fl >> q) & 1u) ? 0xFFu : 0x01u;
+                if constexpr (POTTS)
+                    code = (uint32_t)(pv >> (4u * q)) & 0xFu;
+                else
+                    code = ((fl >> q) & 1u) ? 0xFFu : 0x01u;
                 max_int = max(max_int, S);
                 sq_int += S * S;
                 const uint32_t bin = 31u - (uint32_t)__clz((int)S);
@@ -557,8 +690,8 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
             const uint32_t root = *word_at(s_par, cur) & 0xFFFFu;
             const uint32_t rsite = root / 4u - root / (4u * PS);
             const uint32_t code = (out[q >> 2] >> (8 * (q & 3))) & 0xFFu;
-            lab[q] = (code >= 2u && code < 254u) ? (0x80000000u | (tile * kNodeSlots + code - 2u))
-                                                 : (ty * TW + rsite / TW) * L + tx * TW + rsite % TW;
+            lab[q] = (code >= CB && code < CB + 252u) ? (0x80000000u | (tile * kNodeSlots + code - CB))
+                                                      : (ty * TW + rsite / TW) * L + tx * TW + rsite % TW;
         }
         uint4 *lp = reinterpret_cast<uint4 *>(d.labels + (size_t)gy * L + gx0);
         lp[0] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
@@ -569,18 +702,19 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     {
         // node index of every edge site (all of them belong to nodes)
         uint8_t *eg = d.edge + (size_t)tile * 4u * TW;
-        if (seg == 0u) eg[0 * TW + ly] = (uint8_t)((out[0] & 0xFFu) - 2u);
-        if (seg == RPT - 1u) eg[1 * TW + ly] = (uint8_t)((out[3] >> 24) - 2u);
+        // (every edge byte is a node code, so the bytewise subtraction never borrows)
+        constexpr uint32_t CB4 = CB * 0x01010101u;
+        if (seg == 0u) eg[0 * TW + ly] = (uint8_t)((out[0] & 0xFFu) - CB);
+        if (seg == RPT - 1u) eg[1 * TW + ly] = (uint8_t)((out[3] >> 24) - CB);
         if (ly == 0u)
-            *reinterpret_cast<uint4 *>(eg + 2 * TW + x0) =
-                make_uint4(out[0] - 0x02020202u, out[1] - 0x02020202u, out[2] - 0x02020202u, out[3] - 0x02020202u);
+            *reinterpret_cast<uint4 *>(eg + 2 * TW + x0) = make_uint4(out[0] - CB4, out[1] - CB4, out[2] - CB4, out[3] - CB4);
         if (ly == (uint32_t)TW - 1u)
-            *reinterpret_cast<uint4 *>(eg + 3 * TW + x0) =
-                make_uint4(out[0] - 0x02020202u, out[1] - 0x02020202u, out[2] - 0x02020202u, out[3] - 0x02020202u);
+            *reinterpret_cast<uint4 *>(eg + 3 * TW + x0) = make_uint4(out[0] - CB4, out[1] - CB4, out[2] - CB4, out[3] - CB4);
     }
     // energy and magnetisation packed as (e + 32) | (m + 16) << 16 per lane:
     // the wavefront sums stay below 2^13 and 2^12
-    uint32_t em = (uint32_t)(e_part + 32) | ((uint32_t)(m_part + 16) << 16);
+    // (Potts: the equal pairs alone, at most 32 per lane)
+    uint32_t em = POTTS ? (uint32_t)e_part : (uint32_t)(e_part + 32) | ((uint32_t)(m_part + 16) << 16);
 
     // ---- workgroup reductions -> tile partial
 #pragma unroll
@@ -589,20 +723,32 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         hpk += __shfl_xor(hpk, o, 64);
         max_int = max(max_int, (uint32_t)__shfl_xor((int)max_int, o, 64));
         sq_int += __shfl_xor(sq_int, o, 64);
+        if constexpr (POTTS) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) cpk[i] += __shfl_xor(cpk[i], o, 64);
+        }
     }
     if ((tid & 63u) == 0u) {
         s_red[tid >> 6][0] = (int32_t)em;
         s_red[tid >> 6][1] = (int32_t)hpk;
         s_red[tid >> 6][2] = (int32_t)max_int;
         s_red[tid >> 6][3] = (int32_t)sq_int;
+        if constexpr (POTTS) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_red[tid >> 6][4 + i] = (int32_t)cpk[i];
+        }
     }
     __syncthreads();
     if (tid == 0u) {
         int32_t e = 0, m = 0, mx = 0, sq = 0, b0 = 0, b1 = 0, b2 = 0;
         for (int w = 0; w < NWAVE; ++w) {
             const uint32_t ew = (uint32_t)s_red[w][0], hw = (uint32_t)s_red[w][1];
-            e += (int32_t)(ew & 0xFFFFu) - 32 * 64;
-            m += (int32_t)(ew >> 16) - 16 * 64;
+            if constexpr (POTTS) {
+                e += (int32_t)ew;
+            } else {
+                e += (int32_t)(ew & 0xFFFFu) - 32 * 64;
+                m += (int32_t)(ew >> 16) - 16 * 64;
+            }
             b0 += (int32_t)(hw & 0x3FFu);
             b1 += (int32_t)((hw >> 10) & 0x3FFu);
             b2 += (int32_t)(hw >> 20);
@@ -621,6 +767,13 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         tp[TP_HIST + 1] = b1;
         tp[TP_HIST + 2] = b2;
         for (int b = 3; b < 12; ++b) tp[TP_HIST + b] = (int32_t)s_hist[b];
+        if constexpr (POTTS) {
+            for (int k = 0; k < 8; ++k) {
+                int32_t c = 0;
+                for (int w = 0; w < NWAVE; ++w) c += (int32_t)(((uint32_t)s_red[w][4 + k / 2] >> (16 * (k & 1))) & 0xFFFFu);
+                tp[TP_CNT + k] = c;
+            }
+        }
         d.nk[pc][tile] = s_k;
         uint64_t xe = s_xe[0];
         if constexpr (TW == 64) xe |= (uint64_t)s_xe[1] << 32;
@@ -629,9 +782,9 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     }
 }
 
-template <int TW>
+template <int TW, bool POTTS = false>
 __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
-    tile_body<TW>(d, tile_of_block(blockIdx.x, d.ntiles));
+    tile_body<TW, POTTS>(d, tile_of_block(blockIdx.x, d.ntiles));
 }
 
 // Batched launches run the same bodies over a table of replicas (map
@@ -910,8 +1063,10 @@ __global__ __launch_bounds__(256) void k_relabel(Dev d) {
 // =====================================================================
 __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
     __shared__ uint32_t s_hist[33];
+    __shared__ uint32_t s_cnt[kMaxQ];  // Potts value populations of the group's tiles
     __shared__ uint64_t s_red[4][5];
     if (threadIdx.x < 33u) s_hist[threadIdx.x] = 0u;
+    if (threadIdx.x < (uint32_t)kMaxQ) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
     const uint64_t tsw = *d.tdev;
     const uint32_t t = (uint32_t)tsw, pc = (uint32_t)(tsw & 1u);
@@ -936,7 +1091,8 @@ __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
             const uint32_t node = (g0 + wv + 4u * q) * kNodeSlots + (i - base);
             if (par[node] == node) {
                 const uint32_t S = d.nsize[node];
-                d.rspin[node] = cluster_spin(d.key[node], t, d.seed_lo, d.seed_hi);
+                d.rspin[node] = d.q ? potts_spin(d.key[node], t, d.q, d.seed_lo, d.seed_hi)
+                                    : cluster_spin(d.key[node], t, d.seed_lo, d.seed_hi);
                 ++n;
                 mx = max(mx, (uint64_t)S);
                 sq += (uint64_t)S * S;
@@ -956,6 +1112,9 @@ __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
             sq += (uint32_t)tp[TP_SQ];
             for (int b = 0; b < 12; ++b)
                 if (tp[TP_HIST + b]) atomicAdd(&s_hist[b], (uint32_t)tp[TP_HIST + b]);
+            if (d.q)
+                for (int k = 0; k < kMaxQ; ++k)
+                    if (tp[TP_CNT + k]) atomicAdd(&s_cnt[k], (uint32_t)tp[TP_CNT + k]);
         }
     }
 #pragma unroll
@@ -991,6 +1150,7 @@ __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
         gp[GP_M] = a4;
     }
     if (threadIdx.x < 33u) gp[GP_HIST + threadIdx.x] = s_hist[threadIdx.x];
+    if (threadIdx.x < (uint32_t)kMaxQ) gp[GP_CNT + threadIdx.x] = s_cnt[threadIdx.x];
 }
 
 __global__ __launch_bounds__(256) void k_roots(Dev d) { roots_body(d, blockIdx.x); }
@@ -1030,10 +1190,13 @@ __device__ __forceinline__ void record_fold(const Dev &d, uint32_t begin, uint32
         }
     } else {
         int64_t e = 0, m = 0;
+        uint32_t c[kMaxQ] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
         for (uint32_t item = begin + tid; item < end; item += 256u) {
             const int32_t *tp = d.tpart + (size_t)item * kTilePart;
             e += tp[TP_E];
             m += tp[TP_M];
+            if (d.q)
+                for (int k = 0; k < kMaxQ; ++k) c[k] += (uint32_t)tp[TP_CNT + k];
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -1044,6 +1207,9 @@ __device__ __forceinline__ void record_fold(const Dev &d, uint32_t begin, uint32
             atomicAdd(&a[GP_E], (unsigned long long)e);
             atomicAdd(&a[GP_M], (unsigned long long)m);
         }
+        if (d.q)
+            for (int k = 0; k < kMaxQ; ++k)
+                if (c[k]) atomicAdd(&a[GP_CNT + k], (unsigned long long)c[k]);
     }
 }
 
@@ -1141,16 +1307,18 @@ __global__ __launch_bounds__(256) void k_record_b(const Dev *devs, const uint32_
 // k_resolve: replace node codes by final spins in place and measure the
 // configuration (runs once at the end of every sw_sweep call).
 // =====================================================================
-template <int TW>
+template <int TW, bool POTTS = false>
 __device__ __forceinline__ void resolve_body(const Dev &d, const uint32_t tile) {
     constexpr int NT = TW * TW / 16;
     constexpr uint32_t RPT = TW / 16;
     constexpr int NWAVE = (NT + 63) / 64;
+    constexpr int NPL = POTTS ? 3 : 1;
+    constexpr uint32_t EW = (TW + 31) / 32;
     using Row = typename RowOf<TW>::T;
     __shared__ uint8_t s_tab[256];
-    __shared__ Row s_up[TW + 1];
-    __shared__ uint32_t s_eup[(TW + 31) / 32];
-    __shared__ int32_t s_red[NWAVE][2];
+    __shared__ Row s_up[NPL * (TW + 1)];
+    __shared__ uint32_t s_eup[NPL * EW];
+    __shared__ int32_t s_red[NWAVE][POTTS ? 6 : 2];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t L = d.L, ntx = d.ntx;
@@ -1176,38 +1344,88 @@ __device__ __forceinline__ void resolve_body(const Dev &d, const uint32_t tile) 
         const uint32_t gxe = (gx0 + 16u == L) ? 0u : gx0 + 16u;
         ve = (uint8_t)sp[(size_t)gy * L + gxe];
     }
-    load_table<TW>(d, tile, pp, s_tab, tid);
-    if (tid < (uint32_t)((TW + 31) / 32)) s_eup[tid] = 0u;
+    load_table<TW, POTTS>(d, tile, pp, s_tab, tid);
+    if (tid < NPL * EW) s_eup[tid] = 0u;
     __syncthreads();
-    const uint32_t up = decode16<TW>(v, s_tab);
-    reinterpret_cast<uint16_t *>(s_up)[ly * RPT + seg] = (uint16_t)up;
-    if (ly == TW - 1) {
-        const uint32_t upn = decode16_remote(vn, north, par_prev, d.rspin, nnodes);
-        reinterpret_cast<uint16_t *>(s_up)[TW * RPT + seg] = (uint16_t)upn;
-    }
-    if (seg == RPT - 1) {
-        if (resolve_byte(ve, east, par_prev, d.rspin, nnodes) > 0) atomicOr(&s_eup[ly >> 5], 1u << (ly & 31u));
-    }
-    __syncthreads();
-    const Row rowv = s_up[ly];
-    const uint32_t upN = (uint32_t)(s_up[ly + 1] >> x0) & 0xFFFFu;
-    const uint32_t ebit = (s_eup[ly >> 5] >> (ly & 31u)) & 1u;
-    const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
-    const uint32_t upE = (up >> 1) | (nxt << 15);
-    int32_t e_part = 2 * (__popc(~(up ^ upE) & 0xFFFFu) + __popc(~(up ^ upN) & 0xFFFFu)) - 32;
-    int32_t m_part = 2 * __popc(up) - 16;
-    uint32_t out[4] = {0u, 0u, 0u, 0u};
+    uint32_t up = 0u, pl[3] = {0u, 0u, 0u};
+    if constexpr (POTTS) {
+        decode16_potts(v, s_tab, pl);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) out[q >> 2] |= (((up >> q) & 1u) ? 0x01u : 0xFFu) << (8 * (q & 3));
+        for (int b = 0; b < 3; ++b) reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[ly * RPT + seg] = (uint16_t)pl[b];
+        if (ly == TW - 1) {
+            uint32_t pn[3];
+            decode16_potts_remote(vn, north, par_prev, d.rspin, nnodes, pn);
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[TW * RPT + seg] = (uint16_t)pn[b];
+        }
+        if (seg == RPT - 1) {
+            const uint32_t ev = potts_byte(ve, east, par_prev, d.rspin, nnodes);
+#pragma unroll
+            for (uint32_t b = 0; b < 3u; ++b)
+                if ((ev >> b) & 1u) atomicOr(&s_eup[b * EW + (ly >> 5)], 1u << (ly & 31u));
+        }
+    } else {
+        up = decode16<TW>(v, s_tab);
+        reinterpret_cast<uint16_t *>(s_up)[ly * RPT + seg] = (uint16_t)up;
+        if (ly == TW - 1) {
+            const uint32_t upn = decode16_remote(vn, north, par_prev, d.rspin, nnodes);
+            reinterpret_cast<uint16_t *>(s_up)[TW * RPT + seg] = (uint16_t)upn;
+        }
+        if (seg == RPT - 1) {
+            if (resolve_byte(ve, east, par_prev, d.rspin, nnodes) > 0) atomicOr(&s_eup[ly >> 5], 1u << (ly & 31u));
+        }
+    }
+    __syncthreads();
+    int32_t e_part, m_part = 0;
+    uint32_t cpk[4] = {0u, 0u, 0u, 0u};
+    uint32_t out[4] = {0u, 0u, 0u, 0u};
+    if constexpr (POTTS) {
+        uint32_t dE = 0u, dN = 0u;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const Row rowv = s_up[b * (TW + 1) + ly];
+            const uint32_t pN = (uint32_t)(s_up[b * (TW + 1) + ly + 1] >> x0) & 0xFFFFu;
+            const uint32_t ebit = (s_eup[b * EW + (ly >> 5)] >> (ly & 31u)) & 1u;
+            const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
+            dE |= pl[b] ^ ((pl[b] >> 1) | (nxt << 15));
+            dN |= pl[b] ^ pN;
+        }
+        e_part = __popc(~dE & 0xFFFFu) + __popc(~dN & 0xFFFFu);
+        potts_counts(pl, cpk);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const uint32_t x = ((pl[0] >> q) & 1u) | (((pl[1] >> q) & 1u) << 1) | (((pl[2] >> q) & 1u) << 2);
+            out[q >> 2] |= x << (8 * (q & 3));
+        }
+    } else {
+        const Row rowv = s_up[ly];
+        const uint32_t upN = (uint32_t)(s_up[ly + 1] >> x0) & 0xFFFFu;
+        const uint32_t ebit = (s_eup[ly >> 5] >> (ly & 31u)) & 1u;
+        const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
+        const uint32_t upE = (up >> 1) | (nxt << 15);
+        e_part = 2 * (__popc(~(up ^ upE) & 0xFFFFu) + __popc(~(up ^ upN) & 0xFFFFu)) - 32;
+        m_part = 2 * __popc(up) - 16;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) out[q >> 2] |= (((up >> q) & 1u) ? 0x01u : 0xFFu) << (8 * (q & 3));
+    }
     *reinterpret_cast<uint4 *>(sp + (size_t)gy * L + gx0) = make_uint4(out[0], out[1], out[2], out[3]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         e_part += __shfl_xor(e_part, o, 64);
         m_part += __shfl_xor(m_part, o, 64);
+        if constexpr (POTTS) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) cpk[i] += __shfl_xor(cpk[i], o, 64);
+        }
     }
     if ((tid & 63u) == 0u) {
         s_red[tid >> 6][0] = e_part;
         s_red[tid >> 6][1] = m_part;
+        if constexpr (POTTS) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_red[tid >> 6][2 + i] = (int32_t)cpk[i];
+        }
     }
     __syncthreads();
     if (tid == 0u) {
@@ -1216,14 +1434,22 @@ __device__ __forceinline__ void resolve_body(const Dev &d, const uint32_t tile) 
             e += s_red[w][0];
             m += s_red[w][1];
         }
-        d.tpart[(size_t)tile * kTilePart + TP_E] = e;
-        d.tpart[(size_t)tile * kTilePart + TP_M] = m;
+        int32_t *tp = d.tpart + (size_t)tile * kTilePart;
+        tp[TP_E] = e;
+        tp[TP_M] = m;
+        if constexpr (POTTS) {
+            for (int k = 0; k < 8; ++k) {
+                int32_t c = 0;
+                for (int w = 0; w < NWAVE; ++w) c += (int32_t)(((uint32_t)s_red[w][2 + k / 2] >> (16 * (k & 1))) & 0xFFFFu);
+                tp[TP_CNT + k] = c;
+            }
+        }
     }
 }
 
-template <int TW>
+template <int TW, bool POTTS = false>
 __global__ __launch_bounds__(TW *TW / 16) void k_resolve(Dev d) {
-    resolve_body<TW>(d, tile_of_block(blockIdx.x, d.ntiles));
+    resolve_body<TW, POTTS>(d, tile_of_block(blockIdx.x, d.ntiles));
 }
 
 template <int TW>
@@ -1290,7 +1516,9 @@ hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
     switch (stage) {
     case 0:  // bonds + tile-local clusters
         if (d.dense) k_zero_u64<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(d.dense, n + 1);
-        if (d.tw == 64)
+        if (d.q)
+            k_tile<32, true><<<d.ntiles, 64, 0, s>>>(d);
+        else if (d.tw == 64)
             k_tile<64><<<d.ntiles, 256, 0, s>>>(d);
         else
             k_tile<32><<<d.ntiles, 64, 0, s>>>(d);
@@ -1332,7 +1560,9 @@ hipError_t launch_sweep(const Dev &d, hipStream_t s) {
 
 hipError_t launch_resolve(const Dev &d, hipStream_t s) {
     if (d.le_grid) return hipSuccess;  // that path writes final spins and full records
-    if (d.tw == 64)
+    if (d.q)
+        k_resolve<32, true><<<d.ntiles, 64, 0, s>>>(d);
+    else if (d.tw == 64)
         k_resolve<64><<<d.ntiles, 256, 0, s>>>(d);
     else
         k_resolve<32><<<d.ntiles, 64, 0, s>>>(d);

@@ -1,5 +1,6 @@
-"""q-state Potts sweeps (label-equivalence path) through the C ABI, bit for
-bit against the Potts oracle: records, spins and canonical labels."""
+"""q-state Potts sweeps through the C ABI, on the label-equivalence path and
+on the tile path (32-wide tiles), bit for bit against the Potts oracle:
+records, spins, canonical labels and the dense cluster-size histogram."""
 import math
 
 import numpy as np
@@ -70,7 +71,7 @@ def test_cold_start_and_resume():
 
 def test_potts_configuration_errors():
     with pytest.raises(sw.SwError) as e:
-        sw.Sim(64, 1.0, 1.0, 1, q=3)  # needs the label-equivalence path
+        sw.Sim(64, 1.0, 1.0, 1, q=3, tile=64)  # the Potts tile path uses 32-wide tiles
     assert e.value.code == sw.SW_EINVAL
     with pytest.raises(sw.SwError) as e:
         sw.Sim(64, 1.0, 1.0, 1, q=9, flags=sw.SW_FLAG_LABEL_EQUIV)
@@ -78,3 +79,71 @@ def test_potts_configuration_errors():
     with pytest.raises(sw.SwError) as e:
         sw.Sim(64, 1.0, 1.0, 1, q=1, flags=sw.SW_FLAG_LABEL_EQUIV)
     assert e.value.code == sw.SW_EINVAL
+
+
+def _potts_tile(L, q, beta, seed, **kw):
+    print(f"\n[case] Potts tile path q={q} L={L} beta={beta} seed={seed} {kw}", flush=True)
+    return sw.Sim(L, beta, 1.0, seed, q=q, **kw)
+
+
+@pytest.mark.parametrize("q", [2, 3, 5, 8])
+@pytest.mark.parametrize("L", [32, 96, 160])
+def test_tile_path_matches_oracle(q, L):
+    """Several tiles, a ragged tile count (96 = 3 tiles, 160 = 5), periodic
+    wrap; beta 0 (no bonds), the critical point, an ordered phase."""
+    seed, n = 500 + q + L, 9
+    for beta in (0.0, math.log(1.0 + math.sqrt(q)), 0.4, 2.5):
+        T = oracle.potts_threshold(beta, 1.0)
+        sp = oracle.potts_init(L, seed, q)
+        ref = oracle.potts_run(L, 1.0, T, q, seed, 0, n - 1, sp)
+        last, lab = oracle.potts_sweep(L, 1.0, T, q, seed, n - 1, sp)
+        with _potts_tile(L, q, beta, seed, flags=sw.SW_FLAG_LABELS | sw.SW_FLAG_DENSE_HIST) as s:
+            assert s.threshold == T and s.tile == 32
+            s.sweep(2)
+            s.sweep(n - 2)
+            got = s.series(0, n)
+            _same_records(got[: n - 1], ref, f"tile q={q} L={L} beta={beta}")
+            _same_records(got[n - 1:], np.array([last], dtype=got.dtype), f"tile q={q} L={L} last")
+            assert np.array_equal(s.spins(), sp)
+            assert np.array_equal(s.labels(), lab)
+            h = s.cluster_hist()
+            assert int((h * np.arange(len(h))).sum()) == L * L and h.sum() == last["n_clusters"]
+
+
+def test_tile_path_cold_start_resume_and_label_equivalence_agree():
+    L, q, seed = 128, 4, 21
+    beta = math.log(1.0 + math.sqrt(q))
+    T = oracle.potts_threshold(beta, 1.0)
+    sp = oracle.potts_init(L, seed, q, cold=True)
+    ref = oracle.potts_run(L, 1.0, T, q, seed, 0, 7, sp)
+    with _potts_tile(L, q, beta, seed, init=sw.SW_INIT_COLD) as s, _potts(L, q, beta, seed, init=sw.SW_INIT_COLD) as le:
+        s.sweep(7)
+        le.sweep(7)
+        _same_records(s.series(0, 7), ref, "tile cold")
+        _same_records(le.series(0, 7), ref, "label-equivalence cold")
+        assert np.array_equal(s.spins(), sp) and np.array_equal(le.spins(), sp)
+        state = np.random.default_rng(8).integers(0, q, L * L).astype(np.int8)
+        s.set_spins(state, 1000)
+        s.sweep(3)
+        ref2 = oracle.potts_run(L, 1.0, T, q, seed, 1000, 3, state)
+        _same_records(s.series(1000, 3), ref2, "tile resumed")
+        assert np.array_equal(s.spins(), state)
+
+
+def test_tile_path_large_lattice():
+    """L = 4096 (4096 tiles): two sweeps bit for bit from a GPU checkpoint
+    after 20 sweeps; every record passes the integer invariants."""
+    L, q, seed = 4096, 3, 77
+    beta = math.log(1.0 + math.sqrt(q))
+    T = oracle.potts_threshold(beta, 1.0)
+    with _potts_tile(L, q, beta, seed) as s:
+        s.sweep(20)
+        state = s.spins()
+        assert state.min() >= 0 and state.max() < q
+        s.sweep(2)
+        recs = s.series(0, 22)
+        ref = oracle.potts_run(L, 1.0, T, q, seed, 20, 2, state)
+        _same_records(recs[20:], ref, "L=4096 checkpoint")
+        assert np.array_equal(s.spins(), state)
+        assert np.all(recs["e_sum"] <= 2 * L * L) and np.all(recs["m_sum"] >= L * L // q)
+        assert np.all(recs["hist_log2"].sum(axis=1) == recs["n_clusters"])

@@ -146,9 +146,9 @@ def batched_vs_plain(args):
 
 
 def potts_tile(args):
-    """The q = 3 Potts model on the tile path (32-wide tiles) at its critical
-    point ln(1 + sqrt 3), headline lattice, hot start; per-kernel times from
-    the measurement entry point."""
+    """The q = 3 Potts model on the tile path at its critical point
+    ln(1 + sqrt 3), headline lattice, hot start; per-kernel times from the
+    measurement entry point."""
     import paper_2302_14720_amd as sw
 
     q, L = 3, args.L
@@ -161,8 +161,10 @@ def potts_tile(args):
     s.sync()
     dt = time.perf_counter() - t0
     prof = s.profile(5)
+    tw = s.tile
     s.close()
-    out = {"workload": f"2D q=3 Potts, L={L} periodic, J=1, beta=ln(1+sqrt 3), hot start seed 11, tile path (32-wide tiles)",
+    out = {"workload": f"2D q=3 Potts, L={L} periodic, J=1, beta=ln(1+sqrt 3), hot start seed 11, "
+                       f"tile path ({tw}-wide tiles)",
            "value": L * L * args.potts_steps / dt, "unit": "site-updates/s", "sweeps": args.potts_steps,
            "ms_per_step": dt * 1e3 / args.potts_steps, "kernel_ms": prof}
     print(f"[bench] Potts q=3 tile path L={L}: {out['value']:.4g} site-updates/s, kernel ms {prof}",

@@ -190,9 +190,9 @@ int sw_get_labels(sw_sim *sim, uint32_t *host, int64_t n);
  * (65,536) without converging, -1 for a sim of the default path. */
 int32_t sw_label_passes(sw_sim *sim);
 
-/* q-state Potts model (sw_config.q = 2..8; on the tile path with 32-wide
- * tiles -- tile 0 selects them, tile 64 is SW_EINVAL -- or on the
- * label-equivalence path with SW_FLAG_LABEL_EQUIV; both give the same bits):
+/* q-state Potts model (sw_config.q = 2..8; on the tile path -- 64-wide tiles
+ * for q <= 4, 32-wide tiles above (tile 64 with q > 4 is SW_EINVAL) -- or on
+ * the label-equivalence path with SW_FLAG_LABEL_EQUIV; all give the same bits):
  * spins are 0..q-1 (int8), H = -J sum_<ij> delta(s_i, s_j).  A sweep bonds equal
  * neighbours with p = 1 - exp(-beta J) (T = floor(p 2^32), the same edge
  * words as the Ising model), forms clusters the same way, and gives every

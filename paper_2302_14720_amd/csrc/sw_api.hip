@@ -56,8 +56,9 @@ uint32_t bond_threshold(double beta, double J) {
 }
 
 int resolve_tile(const sw_config &c) {
-    if (c.q != 0) return 32;  // the Potts tile path uses 32-wide tiles
-    if (c.tile == 0) return (c.L % 64 == 0) ? 64 : 32;
+    // the Potts model fits its values below the node codes of a 64-wide
+    // tile only for q <= 4
+    if (c.tile == 0) return (c.L % 64 == 0 && c.q <= 4) ? 64 : 32;
     return c.tile;
 }
 
@@ -88,8 +89,8 @@ int validate(const sw_config *c) {
     if (c->ring < 0 || c->ring > (int64_t)1 << 30) return fail(SW_EINVAL, "ring must be in [0, 2^30]");
     if (c->q != 0 && (c->q < 2 || c->q > swmi::kMaxQ))
         return fail(SW_EINVAL, "q must be 0 (Ising) or in [2, 8] (Potts)");
-    if (c->q != 0 && c->tile == 64 && !(c->flags & SW_FLAG_LABEL_EQUIV))
-        return fail(SW_EINVAL, "the q-state Potts model uses 32-wide tiles (tile 0 or 32)");
+    if (c->q > 4 && c->tile == 64 && !(c->flags & SW_FLAG_LABEL_EQUIV))
+        return fail(SW_EINVAL, "the q-state Potts model with q > 4 uses 32-wide tiles (tile 0 or 32)");
     return SW_OK;
 }
 

@@ -177,10 +177,12 @@ __device__ __forceinline__ uint32_t byte_at(const uint4 &v, int q) {
 // of this tile's previous output to its spin as an up bit (1 for +1): final
 // spins 0x01 / 0xFF map to themselves, node code 2 + k to the spin of node
 // k's root.
-// Potts model on the tile path (32-wide tiles, so at most 124 nodes per
-// tile): a byte below kPottsCode is a final value 0..7, kPottsCode + k
-// refers to node k of its tile.
-constexpr uint32_t kPottsCode = 8;
+// Output bytes of the Potts model on the tile path: a byte below
+// potts_code<TW>() is a final value, potts_code<TW>() + k refers to node k of
+// its tile.  A 32-wide tile has at most 124 nodes, so all values 0..7 fit
+// below 8; a 64-wide tile has up to 252 nodes, which leaves bytes 0..3 for
+// the values of q <= 4.
+template <int TW> constexpr uint32_t potts_code() { return TW == 64 ? 4u : 8u; }
 
 template <int TW, bool POTTS>
 __device__ __forceinline__ void load_table(const Dev &d, uint32_t tile, uint32_t pp, uint8_t *s_tab,
@@ -194,7 +196,7 @@ __device__ __forceinline__ void load_table(const Dev &d, uint32_t tile, uint32_t
         uint32_t k;
         if constexpr (POTTS) {
             val = (uint8_t)(b & 7u);
-            k = b - kPottsCode;
+            k = b - potts_code<TW>();
         } else {
             val = b == 0xFFu ? 0u : 1u;
             k = b - 2u;
@@ -226,9 +228,10 @@ __device__ __forceinline__ uint32_t decode16_remote(const uint4 &v, uint32_t til
 }
 
 // Potts value (0..7) of a byte of tile `tile`'s previous output.
+template <int TW>
 __device__ __forceinline__ uint32_t potts_byte(uint32_t b, uint32_t tile, const uint32_t *par_prev,
                                                const int8_t *rspin, uint32_t nnodes) {
-    const uint32_t k = b - kPottsCode;
+    const uint32_t k = b - potts_code<TW>();
     if (k < 252u) {
         uint32_t p = par_prev[tile * kNodeSlots + k];
         p = p < nnodes ? p : 0u;
@@ -249,12 +252,13 @@ __device__ __forceinline__ void decode16_potts(const uint4 &v, const uint8_t *s_
     }
 }
 
+template <int TW>
 __device__ __forceinline__ void decode16_potts_remote(const uint4 &v, uint32_t tile, const uint32_t *par_prev,
                                                       const int8_t *rspin, uint32_t nnodes, uint32_t pl[3]) {
     pl[0] = pl[1] = pl[2] = 0u;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const uint32_t x = potts_byte(byte_at(v, q), tile, par_prev, rspin, nnodes);
+        const uint32_t x = potts_byte<TW>(byte_at(v, q), tile, par_prev, rspin, nnodes);
         pl[0] |= (x & 1u) << q;
         pl[1] |= ((x >> 1) & 1u) << q;
         pl[2] |= (x >> 2) << q;
@@ -290,10 +294,11 @@ __device__ __forceinline__ void potts_counts(const uint32_t pl[3], uint32_t cpk[
 // unions of run starts; each run start is then pointed at its root, which
 // collects the cluster size and, after numbering, the output byte.
 // =====================================================================
-// POTTS: the q-state Potts model (32-wide tiles): spins are values 0..7
-// held as three bit planes, bonds join equal values, an interior cluster
-// takes the Potts value of its root site, node codes start at kPottsCode,
-// and the tile measures equal pairs and the population of every value.
+// POTTS: the q-state Potts model (64-wide tiles for q <= 4, else 32-wide):
+// spins are values held as three bit planes, bonds join equal values, an
+// interior cluster takes the Potts value of its root site, node codes start
+// at potts_code<TW>(), and the tile measures equal pairs and the population
+// of every value.
 template <int TW, bool POTTS = false>
 __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     using Row = typename RowOf<TW>::T;
@@ -304,8 +309,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     constexpr int NWAVE = (NT + 63) / 64;
     constexpr int NPL = POTTS ? 3 : 1;  // bit planes of a spin
     constexpr uint32_t EW = (TW + 31) / 32;
-    constexpr uint32_t CB = POTTS ? kPottsCode : 2u;  // output byte of node 0
-    static_assert(!POTTS || TW == 32, "the Potts tile path uses 32-wide tiles");
+    constexpr uint32_t CB = POTTS ? potts_code<TW>() : 2u;  // output byte of node 0
 
     // One word per site, rows padded to PS = TW + 1 words so that the 16
     // sites a lane gathers at equal offsets fall in distinct banks.  Low 16
@@ -313,8 +317,13 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     // work list while the unions run, then the cluster size (roots), then
     // the root's output byte.
     constexpr uint32_t PS = TW + 1;
-    __shared__ uint32_t s_par[TW * PS];
-    __shared__ Row s_up[NPL * (TW + 1)];
+    __shared__ __align__(16) uint32_t s_par[TW * PS];
+    // spin masks (Potts: bit planes); they are dead before s_par is first
+    // written, so the 64-wide Potts tile keeps its three planes in s_par
+    constexpr bool UP_IN_PAR = POTTS && TW == 64;
+    static_assert(!UP_IN_PAR || 3 * (TW + 1) * sizeof(Row) <= TW * PS * 4, "planes must fit in s_par");
+    __shared__ Row s_up_own[UP_IN_PAR ? 1 : NPL * (TW + 1)];
+    Row *const s_up = UP_IN_PAR ? reinterpret_cast<Row *>(s_par) : s_up_own;
     __shared__ Row s_ebnb[2 * TW];  // bond masks to E (rows 0..TW-1) and N (rows TW..2TW-1)
     Row *const s_eb = s_ebnb;
     Row *const s_nb = s_ebnb + TW;
@@ -411,13 +420,13 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         for (int b = 0; b < 3; ++b) reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[ly * RPT + seg] = (uint16_t)pl[b];
         if (ly == TW - 1) {
             uint32_t pn[3];
-            decode16_potts_remote(vn, north, par_prev, d.rspin, nnodes, pn);
+            decode16_potts_remote<TW>(vn, north, par_prev, d.rspin, nnodes, pn);
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[TW * RPT + seg] = (uint16_t)pn[b];
         }
         if (seg == RPT - 1) {
-            const uint32_t ev = potts_byte(ve, east, par_prev, d.rspin, nnodes);
+            const uint32_t ev = potts_byte<TW>(ve, east, par_prev, d.rspin, nnodes);
 #pragma unroll
             for (uint32_t b = 0; b < 3u; ++b)
                 if ((ev >> b) & 1u) atomicOr(&s_eup[b * EW + (ly >> 5)], 1u << (ly & 31u));
@@ -1354,13 +1363,13 @@ __device__ __forceinline__ void resolve_body(const Dev &d, const uint32_t tile) 
         for (int b = 0; b < 3; ++b) reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[ly * RPT + seg] = (uint16_t)pl[b];
         if (ly == TW - 1) {
             uint32_t pn[3];
-            decode16_potts_remote(vn, north, par_prev, d.rspin, nnodes, pn);
+            decode16_potts_remote<TW>(vn, north, par_prev, d.rspin, nnodes, pn);
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[TW * RPT + seg] = (uint16_t)pn[b];
         }
         if (seg == RPT - 1) {
-            const uint32_t ev = potts_byte(ve, east, par_prev, d.rspin, nnodes);
+            const uint32_t ev = potts_byte<TW>(ve, east, par_prev, d.rspin, nnodes);
 #pragma unroll
             for (uint32_t b = 0; b < 3u; ++b)
                 if ((ev >> b) & 1u) atomicOr(&s_eup[b * EW + (ly >> 5)], 1u << (ly & 31u));
@@ -1516,7 +1525,9 @@ hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
     switch (stage) {
     case 0:  // bonds + tile-local clusters
         if (d.dense) k_zero_u64<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(d.dense, n + 1);
-        if (d.q)
+        if (d.q && d.tw == 64)
+            k_tile<64, true><<<d.ntiles, 256, 0, s>>>(d);
+        else if (d.q)
             k_tile<32, true><<<d.ntiles, 64, 0, s>>>(d);
         else if (d.tw == 64)
             k_tile<64><<<d.ntiles, 256, 0, s>>>(d);
@@ -1560,7 +1571,9 @@ hipError_t launch_sweep(const Dev &d, hipStream_t s) {
 
 hipError_t launch_resolve(const Dev &d, hipStream_t s) {
     if (d.le_grid) return hipSuccess;  // that path writes final spins and full records
-    if (d.q)
+    if (d.q && d.tw == 64)
+        k_resolve<64, true><<<d.ntiles, 256, 0, s>>>(d);
+    else if (d.q)
         k_resolve<32, true><<<d.ntiles, 64, 0, s>>>(d);
     else if (d.tw == 64)
         k_resolve<64><<<d.ntiles, 256, 0, s>>>(d);

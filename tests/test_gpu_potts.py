@@ -71,7 +71,7 @@ def test_cold_start_and_resume():
 
 def test_potts_configuration_errors():
     with pytest.raises(sw.SwError) as e:
-        sw.Sim(64, 1.0, 1.0, 1, q=3, tile=64)  # the Potts tile path uses 32-wide tiles
+        sw.Sim(64, 1.0, 1.0, 1, q=5, tile=64)  # q > 4 needs 32-wide tiles
     assert e.value.code == sw.SW_EINVAL
     with pytest.raises(sw.SwError) as e:
         sw.Sim(64, 1.0, 1.0, 1, q=9, flags=sw.SW_FLAG_LABEL_EQUIV)
@@ -86,19 +86,21 @@ def _potts_tile(L, q, beta, seed, **kw):
     return sw.Sim(L, beta, 1.0, seed, q=q, **kw)
 
 
-@pytest.mark.parametrize("q", [2, 3, 5, 8])
-@pytest.mark.parametrize("L", [32, 96, 160])
-def test_tile_path_matches_oracle(q, L):
-    """Several tiles, a ragged tile count (96 = 3 tiles, 160 = 5), periodic
-    wrap; beta 0 (no bonds), the critical point, an ordered phase."""
+@pytest.mark.parametrize("q", [2, 3, 4, 5, 8])
+@pytest.mark.parametrize("L,tile", [(32, 0), (96, 0), (160, 0), (64, 0), (192, 0), (128, 32)])
+def test_tile_path_matches_oracle(q, L, tile):
+    """Several tiles, ragged tile counts (96 = 3 tiles of 32, 192 = 3 tiles of
+    64), periodic wrap; 64-wide tiles for q <= 4 when L allows, else 32-wide;
+    beta 0 (no bonds), the critical point, an ordered phase."""
     seed, n = 500 + q + L, 9
+    want_tile = tile if tile else (64 if q <= 4 and L % 64 == 0 else 32)
     for beta in (0.0, math.log(1.0 + math.sqrt(q)), 0.4, 2.5):
         T = oracle.potts_threshold(beta, 1.0)
         sp = oracle.potts_init(L, seed, q)
         ref = oracle.potts_run(L, 1.0, T, q, seed, 0, n - 1, sp)
         last, lab = oracle.potts_sweep(L, 1.0, T, q, seed, n - 1, sp)
-        with _potts_tile(L, q, beta, seed, flags=sw.SW_FLAG_LABELS | sw.SW_FLAG_DENSE_HIST) as s:
-            assert s.threshold == T and s.tile == 32
+        with _potts_tile(L, q, beta, seed, tile=tile, flags=sw.SW_FLAG_LABELS | sw.SW_FLAG_DENSE_HIST) as s:
+            assert s.threshold == T and s.tile == want_tile
             s.sweep(2)
             s.sweep(n - 2)
             got = s.series(0, n)
@@ -130,10 +132,12 @@ def test_tile_path_cold_start_resume_and_label_equivalence_agree():
         assert np.array_equal(s.spins(), state)
 
 
-def test_tile_path_large_lattice():
-    """L = 4096 (4096 tiles): two sweeps bit for bit from a GPU checkpoint
-    after 20 sweeps; every record passes the integer invariants."""
-    L, q, seed = 4096, 3, 77
+@pytest.mark.parametrize("q", [3, 6])
+def test_tile_path_large_lattice(q):
+    """L = 4096 (4096 tiles of 64 for q = 3, 16384 of 32 for q = 6): two
+    sweeps bit for bit from a GPU checkpoint after 20 sweeps; every record
+    passes the integer invariants."""
+    L, seed = 4096, 77
     beta = math.log(1.0 + math.sqrt(q))
     T = oracle.potts_threshold(beta, 1.0)
     with _potts_tile(L, q, beta, seed) as s:

@@ -112,3 +112,42 @@ def test_grid_batch_5000_sweeps():
             s.sweep(n)
             _same_records(recs[r], s.series(n - ring, ring), f"replica {r}")
             assert np.array_equal(spins[r], s.spins())
+
+
+def test_L32768_largest_lattice():
+    """The largest lattice the library accepts (L = 32768, N = 2^30): four
+    sweeps with labels; E and M recomputed from the spins; canonical labels;
+    on 2^17 sampled sites the new spin is its root's flip bit and every bond
+    drawn from the checkpointed spins joins sites with equal labels."""
+    L, seed = 32768, 13
+    N = L * L
+    T = oracle.threshold(BETA_C, 1.0)
+    print(f"\n[case] L={L} beta_c seed={seed} with labels", flush=True)
+    with sw.Sim(L, BETA_C, 1.0, seed, flags=sw.SW_FLAG_LABELS) as s:
+        s.sweep(3)
+        prev = s.spins()
+        s.sweep(1)
+        recs = s.series(0, 4)
+        _invariants(recs, N, "L=32768")
+        sp = s.spins()
+        lab = s.labels()
+    t = 3
+    assert int(sp.sum(dtype=np.int64)) == int(recs["m_sum"][-1])
+    g = sp.reshape(L, L)
+    e = int(np.sum(g * np.roll(g, -1, axis=1), dtype=np.int64)) + int(np.sum(g * np.roll(g, -1, axis=0), dtype=np.int64))
+    assert e == int(recs["e_sum"][-1])
+    rng = np.random.default_rng(5)
+    sample = rng.integers(0, N, 1 << 17)
+    roots = lab[sample]
+    assert np.all(roots <= sample) and np.all(lab[roots] == roots)
+    flips = np.array([oracle.flip_spin(seed, t, int(r)) for r in roots[:4096]])
+    assert np.array_equal(sp[sample[:4096]], flips)
+    pb = prev.reshape(L, L)
+    for s0 in sample[:2048].tolist():
+        y, x = divmod(s0, L)
+        w = oracle.philox4x32_10([s0 >> 1, t, 0, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        east, north = y * L + (x + 1) % L, ((y + 1) % L) * L + x
+        if pb[y, x] == pb[y, (x + 1) % L] and w[2 * (s0 & 1)] < T:
+            assert lab[s0] == lab[east]
+        if pb[y, x] == pb[(y + 1) % L, x] and w[2 * (s0 & 1) + 1] < T:
+            assert lab[s0] == lab[north]

@@ -172,6 +172,39 @@ def potts_tile(args):
     return out
 
 
+CUBIC_WORKLOADS = (("ising", 0, 0.2216544), ("potts_q3", 3, 0.5505))
+
+
+def cubic(args):
+    """The simple cubic lattice on 16^3 bricks (the default 3D path): 3D
+    Ising at its critical coupling (numerical estimate 0.2216544) and 3D q = 3
+    Potts near its transition, L = 512 (134 M sites), hot start."""
+    import paper_2302_14720_amd as sw
+
+    L = 512
+    out = {"unit": "site-updates/s", "sites": L ** 3}
+    for name, q, beta in CUBIC_WORKLOADS:
+        s = sw.Sim(L, beta, 1.0, 13, q=q, dims=3)
+        s.sweep(3)
+        s.sync()
+        t0 = time.perf_counter()
+        s.sweep(args.cubic_steps)
+        s.sync()
+        dt = time.perf_counter() - t0
+        prof = s.profile(3)
+        s.close()
+        out[name] = {"workload": f"3D {'Ising' if q == 0 else 'q=3 Potts'}, L={L} periodic, J=1, beta={beta}, "
+                                 f"hot start seed 13, 16^3 bricks",
+                     "value": L ** 3 * args.cubic_steps / dt, "ms_per_step": dt * 1e3 / args.cubic_steps,
+                     "sweeps": args.cubic_steps,
+                     "kernel_ms": {"bricks": prof["tile"], "face_unions_and_flatten": prof["union"],
+                                   "spins_and_sizes": prof["flatten"], "statistics": prof["roots"],
+                                   "record": prof["record"]}}
+        print(f"[bench] cubic {name} L={L}: {out[name]['value']:.4g} site-updates/s, {out[name]['kernel_ms']}",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def serving(args):
     """Continuous batching: jobs arrive as a Poisson process (L log-uniform in
     [128, 4096] rounded to 32, beta uniform in [0.35, 0.55], sweeps uniform in
@@ -265,8 +298,9 @@ def label_equivalence(args, tile_rate):
                                  "sweeps_from_hot_start": 3 + args.le_steps}
         s.close()
         print(f"[bench] Potts q=3 L={L}: {out[f'potts_q3_L{L}']}", file=sys.stderr, flush=True)
-    # the simple cubic lattice (same path): 3D Ising at its critical coupling
-    # (numerical estimate 0.2216544) and 3D q = 3 Potts near its transition
+    # the simple cubic lattice on this path: 3D Ising at its critical
+    # coupling (numerical estimate 0.2216544) and 3D q = 3 Potts near its
+    # transition (the default 16^3-brick path is timed in its own leg)
     Lc = 512
     for name, q, beta in (("cubic_ising", 0, 0.2216544), ("cubic_potts_q3", 3, 0.5505)):
         s = sw.Sim(Lc, beta, 1.0, 13, q=q, dims=3, flags=sw.SW_FLAG_LABEL_EQUIV)
@@ -309,6 +343,8 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the serving leg, jobs/s")
     ap.add_argument("--potts-steps", type=int, default=50,
                     help="timed sweeps of the q = 3 Potts model on the tile path (0 = skip)")
+    ap.add_argument("--cubic-steps", type=int, default=20,
+                    help="timed sweeps of the simple cubic lattice on 16^3 bricks (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for "
                          "HBM byte counters)")
@@ -435,6 +471,7 @@ def main() -> int:
         "batched": None if args.no_batched else batched_vs_plain(args),
         "serving": serving(args) if args.serve_jobs > 0 else None,
         "potts_tile": potts_tile(args) if args.potts_steps > 0 else None,
+        "cubic": cubic(args) if args.cubic_steps > 0 else None,
         "label_equivalence": label_equivalence(args, value) if args.le_steps > 0 else None,
     }
     if not args.no_cpu_baseline:

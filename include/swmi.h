@@ -203,8 +203,11 @@ int32_t sw_label_passes(sw_sim *sim);
  * population of the most populated value; cluster statistics as for Ising.
  * sw_set_spins takes values 0..q-1. */
 
-/* Simple cubic lattice (sw_config.dims = 3, needs SW_FLAG_LABEL_EQUIV; L a
- * multiple of 16 in [16, 1616], so that N = L^3 < 2^32): the same sweep on
+/* Simple cubic lattice (sw_config.dims = 3; L a multiple of 16 in
+ * [16, 1616], so that N = L^3 < 2^32; clusters are formed in 16^3 bricks and
+ * joined across brick faces, or with SW_FLAG_LABEL_EQUIV by the paper's
+ * label equivalence; both give the same bits; sw_tile gives 16 for the
+ * bricks and 0 for label equivalence): the same sweep on
  * the L x L x L periodic lattice, for the Ising model (q = 0) and the Potts
  * model (q = 2..8).  Site s = (z L + y) L + x, x fastest; each site owns the
  * edges to its +x, +y and +z neighbours (3N edges), and the word of edge

@@ -71,8 +71,6 @@ int validate(const sw_config *c) {
     if (!c) return fail(SW_EINVAL, "config is NULL");
     if (c->dims != 0 && c->dims != 2 && c->dims != 3) return fail(SW_EINVAL, "dims must be 0, 2 or 3");
     if (c->dims == 3) {
-        if (!(c->flags & SW_FLAG_LABEL_EQUIV))
-            return fail(SW_EINVAL, "the simple cubic lattice runs on the label-equivalence path (SW_FLAG_LABEL_EQUIV)");
         if (c->L < 16 || c->L > 1616 || c->L % 16 != 0)
             return fail(SW_EINVAL, "L of the simple cubic lattice must be a multiple of 16 in [16, 1616]");
     } else if (c->L < 32 || c->L > 32768 || c->L % 32 != 0) {
@@ -89,17 +87,18 @@ int validate(const sw_config *c) {
     if (c->ring < 0 || c->ring > (int64_t)1 << 30) return fail(SW_EINVAL, "ring must be in [0, 2^30]");
     if (c->q != 0 && (c->q < 2 || c->q > swmi::kMaxQ))
         return fail(SW_EINVAL, "q must be 0 (Ising) or in [2, 8] (Potts)");
-    if (c->q > 4 && c->tile == 64 && !(c->flags & SW_FLAG_LABEL_EQUIV))
+    if (c->q > 4 && c->tile == 64 && !(c->flags & SW_FLAG_LABEL_EQUIV) && c->dims != 3)
         return fail(SW_EINVAL, "the q-state Potts model with q > 4 uses 32-wide tiles (tile 0 or 32)");
     return SW_OK;
 }
 
 Layout layout_of(const sw_config &c) {
     const size_t L = (size_t)c.L, N = sites_of(c);
-    const bool le = (c.flags & SW_FLAG_LABEL_EQUIV) != 0u;
+    // the label-equivalence path and the cubic bricks keep labels in global
+    // memory and no tile structures; their group partials are one per
+    // kLeChunk sites
+    const bool le = (c.flags & SW_FLAG_LABEL_EQUIV) != 0u || c.dims == 3;
     const size_t tw = (size_t)resolve_tile(c);
-    // the label-equivalence path keeps no tile structures; its group
-    // partials are one per kLeChunk sites
     const size_t ntiles = le ? 0 : (L / tw) * (L / tw);
     const size_t ngroups = le ? (N + swmi::kLeChunk - 1) / swmi::kLeChunk
                               : (ntiles + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
@@ -172,13 +171,17 @@ Dev make_dev(const sw_config &c, char *base, const Layout &lo) {
     d.acc = (uint64_t *)(base + lo.acc);
     d.tdev = (uint64_t *)(base + lo.tdev);
     d.ring = (sw_obs *)(base + lo.ring);
-    const bool le = (c.flags & SW_FLAG_LABEL_EQUIV) != 0u;
+    const bool le = (c.flags & SW_FLAG_LABEL_EQUIV) != 0u || c.dims == 3;
     d.labels = (le || (c.flags & SW_FLAG_LABELS)) ? (uint32_t *)(base + lo.labels) : nullptr;
     d.dense = (c.flags & SW_FLAG_DENSE_HIST) ? (uint64_t *)(base + lo.dense) : nullptr;
     if (le) {
         d.ntiles = 0;
         d.ntx = 0;
         d.ngroups = (uint32_t)((d.nsite + swmi::kLeChunk - 1) / swmi::kLeChunk);
+        if (c.dims == 3 && !(c.flags & SW_FLAG_LABEL_EQUIV)) {
+            d.brick = 1u;
+            d.tw = swmi::kBrick;
+        }
         d.le_mask = (uint8_t *)(base + lo.le_mask);
         d.le_cnt = (uint32_t *)(base + lo.le_cnt);
         d.le_rsp = (int8_t *)(base + lo.le_rsp);
@@ -559,7 +562,7 @@ int32_t sw_label_passes(sw_sim *s) {
 uint32_t sw_threshold(const sw_sim *s) { return s ? s->dev.T : 0u; }
 int64_t sw_next_sweep(const sw_sim *s) { return s ? (int64_t)s->next_sweep : -1; }
 int32_t sw_lattice(const sw_sim *s) { return s ? (int32_t)s->dev.L : 0; }
-int32_t sw_tile(const sw_sim *s) { return s ? (s->dev.le_grid ? 0 : (int32_t)s->dev.tw) : 0; }
+int32_t sw_tile(const sw_sim *s) { return s ? (s->dev.le_grid ? 0 : (int32_t)s->dev.tw) : 0; }  // brick side for cubic
 int64_t sw_sites(const sw_sim *s) { return s ? (int64_t)s->dev.nsite : -1; }
 
 void sw_destroy(sw_sim *s) {

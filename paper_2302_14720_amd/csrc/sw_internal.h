@@ -71,7 +71,8 @@ struct Dev {
     uint32_t ring_cap;
     uint32_t le_grid;     // workgroups of the cooperative labelling kernel (0: tile path)
     uint32_t q;           // 0: Ising; 2..kMaxQ: q-state Potts (label-equivalence path)
-    uint32_t dims;        // 2: L x L; 3: L x L x L (label-equivalence path)
+    uint32_t dims;        // 2: L x L; 3: L x L x L (labels in global memory)
+    uint32_t brick;       // 1: simple cubic lattice on kBrick^3 bricks (else label equivalence)
     uint64_t nsite;       // N = L^dims
     double J;
 };
@@ -102,11 +103,14 @@ struct BatchDev {
     uint32_t n, ntiles, nwmap, ngroups, nugroups, tw;
 };
 
-// Label-equivalence path: stages 0..4 of a sweep (bonds, iterated labelling,
-// new spins and sizes, statistics, record), and the cooperative grid size.
+// Paths with labels in global memory: stages 0..4 of a sweep (bonds and, for
+// cubic bricks, brick-local clusters; global labelling by iterated label
+// equivalence or by union-find across brick faces; new spins and sizes;
+// statistics; record), and the cooperative grid size of label equivalence.
 hipError_t launch_le_stage(const Dev &d, int stage, hipStream_t s);
 uint32_t le_grid_size(uint32_t dims);
 constexpr uint32_t kLeChunk = 4096;  // sites per workgroup in the per-site passes
+constexpr uint32_t kBrick = 16;      // side of a brick of the simple cubic lattice
 enum { LE_PASSES = 3, LE_STATUS = 4 };
 
 hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s);

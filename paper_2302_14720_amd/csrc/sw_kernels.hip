@@ -5,6 +5,7 @@
 // through the LDS union-find.
 #include "sw_internal.h"
 #include "sw_philox.h"
+#include "sw_uf.h"
 
 namespace swmi {
 namespace {
@@ -34,24 +35,7 @@ __device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t n) {
 }
 
 // ---------------------------------------------------------------- LDS union-find
-__device__ __forceinline__ uint32_t lds_load(uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-// Roots are the smallest index of their set and every parent is smaller
-// than its child.  Path halving lowers entries with atomicMin: a plain store
-// could overwrite a fully compressed entry (the root) with a larger ancestor
-// read earlier by another thread, whereas with min-updates every entry only
-// ever decreases towards its root.
-__device__ __forceinline__ uint32_t lds_find(uint32_t *par, uint32_t a) {
-    while (true) {
-        const uint32_t p = lds_load(&par[a]);
-        if (p == a) return a;
-        const uint32_t gp = lds_load(&par[p]);
-        if (gp == p) return p;
-        atomicMin(&par[a], gp);
-        a = gp;
-    }
-}
+// (the plain-index helpers are in sw_uf.h)
 // The tile kernel's parent words hold byte offsets into the LDS array (so a
 // parent is directly a load address) and carry other data in their high
 // halves (a work list while the unions run).
@@ -97,62 +81,7 @@ __device__ __forceinline__ uint32_t lds_root_b(uint32_t *par, uint32_t a) {
     }
 }
 
-// Root of a once the unions are done (read-only; the high half of a root's
-// word may already hold its cluster size).
-__device__ __forceinline__ uint32_t lds_root(const uint32_t *par, uint32_t a) {
-    while (true) {
-        const uint32_t p = par[a] & 0xFFFFu;
-        if (p == a) return a;
-        a = p;
-    }
-}
-__device__ __forceinline__ void lds_union(uint32_t *par, uint32_t a, uint32_t b) {
-    while (true) {
-        a = lds_find(par, a);
-        b = lds_find(par, b);
-        if (a == b) return;
-        if (a > b) { const uint32_t tmp = a; a = b; b = tmp; }
-        uint32_t expected = b;
-        if (__hip_atomic_compare_exchange_strong(&par[b], &expected, a, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-            return;
-    }
-}
 
-// ---------------------------------------------------------- global union-find
-// A root is linked under the root with the smaller node index, so parents
-// always have smaller indices than their children and the structure stays
-// a forest whatever order the unions run in.  The cluster's smallest site
-// is gathered separately (k_flatten takes the minimum of the nodes' keys
-// into the root's key), so finds never read keys.
-__device__ __forceinline__ uint32_t g_load(uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void g_store(uint32_t *p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// Both finds advance together (their loads overlap), each with path
-// halving: a node is re-pointed at its grandparent, which is an ancestor
-// whatever other unions did meanwhile.
-__device__ __forceinline__ void g_union(uint32_t *par, uint32_t a, uint32_t b) {
-    while (true) {
-        while (true) {
-            const uint32_t pa = g_load(&par[a]), pb = g_load(&par[b]);
-            if (pa == a && pb == b) break;
-            const uint32_t ga = g_load(&par[pa]), gb = g_load(&par[pb]);
-            if (ga != pa) g_store(&par[a], ga);
-            if (gb != pb) g_store(&par[b], gb);
-            a = ga;
-            b = gb;
-        }
-        if (a == b) return;
-        if (a > b) { const uint32_t tmp = a; a = b; b = tmp; }
-        uint32_t expected = b;
-        if (__hip_atomic_compare_exchange_strong(&par[b], &expected, a, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            return;
-    }
-}
 
 // Spin (+1/-1) encoded by a byte of the previous sweep's output that belongs
 // to tile `tile`: final spins are 0x01 / 0xFF, a code 2 + k refers to node k
@@ -809,6 +738,9 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile_b(const Dev *devs, const u
 // k_union: bonds that leave a tile through its E or N edge join the nodes
 // on both sides (Sec. 2.3, global part).  One wavefront per tile.
 // =====================================================================
+// The global union-find links nodes by index (sw_uf.h); the cluster's
+// smallest site is gathered separately (k_flatten takes the minimum of the
+// nodes' keys into the root's key), so finds never read keys.
 template <int TW>
 __device__ __forceinline__ void union_body(const Dev &d, const uint32_t tile, const uint32_t dir) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -1513,7 +1445,7 @@ hipError_t launch_init(const Dev &d, int cold, hipStream_t s) {
 
 hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
     const size_t n = d.nsite;
-    if (d.le_grid) {  // label-equivalence path
+    if (d.le_grid || d.brick) {  // labels in global memory (label equivalence, cubic bricks)
         if (stage == 0 && d.dense) k_zero_u64<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(d.dense, n + 1);
         if (stage != 4) {
             const hipError_t e = hipGetLastError();
@@ -1570,7 +1502,7 @@ hipError_t launch_sweep(const Dev &d, hipStream_t s) {
 }
 
 hipError_t launch_resolve(const Dev &d, hipStream_t s) {
-    if (d.le_grid) return hipSuccess;  // that path writes final spins and full records
+    if (d.le_grid || d.brick) return hipSuccess;  // those paths write final spins and full records
     if (d.q && d.tw == 64)
         k_resolve<64, true><<<d.ntiles, 256, 0, s>>>(d);
     else if (d.q)

@@ -14,6 +14,7 @@
 
 #include "sw_internal.h"
 #include "sw_philox.h"
+#include "sw_uf.h"
 
 namespace swmi {
 namespace {
@@ -279,6 +280,195 @@ __global__ __launch_bounds__(256) void k_le_stats(Dev d) {
     for (uint32_t i = threadIdx.x; i < (uint32_t)GP_END; i += 256u) gp[i] = s_acc[i];
 }
 
+// =====================================================================
+// Simple cubic lattice on 16^3 bricks (the default for dims = 3): bonds and
+// the connected components of the bonds inside each brick in LDS; then one
+// union-find in global memory over the bonds that cross brick faces, with
+// the label array itself as the parent array; then every label is pointed
+// at its root.  Roots are always the smallest index (sw_uf.h), so the final
+// label of a site is the smallest site of its cluster, as on the other
+// paths.  Cluster sizes are summed from the brick-local component sizes
+// (one atomic per local component); the statistics and the record are
+// those of the label-equivalence path.
+// =====================================================================
+__device__ __forceinline__ uint32_t byte_of(const uint4 &v, uint32_t j) {
+    const uint32_t w = j < 4u ? v.x : j < 8u ? v.y : j < 12u ? v.z : v.w;
+    return (w >> (8u * (j & 3u))) & 0xFFu;
+}
+
+// One workgroup per brick; thread (y, z) owns the brick's x-row of 16 sites
+// at (y, z).  A site's brick-local index (z * 16 + y) * 16 + x orders the
+// sites of a brick as their global indices do, so the local root (smallest
+// local index) is the component's smallest site.
+__global__ __launch_bounds__(256) void k_brick3(Dev d) {
+    __shared__ uint32_t s_par[kBrick * kBrick * kBrick];
+    __shared__ uint32_t s_ex[kBrick * kBrick];
+    const uint32_t L = d.L, nb = L / kBrick;
+    const uint32_t b = blockIdx.x;
+    const uint32_t bx = b % nb, by = (b / nb) % nb, bz = b / (nb * nb);
+    const uint32_t tid = threadIdx.x, y = tid & 15u, z = tid >> 4;
+    const uint32_t gx0 = bx * kBrick, gy = by * kBrick + y, gz = bz * kBrick + z;
+    const uint32_t gyn = gy + 1u == L ? 0u : gy + 1u, gzn = gz + 1u == L ? 0u : gz + 1u;
+    const uint32_t s0 = (gz * L + gy) * L + gx0;  // N < 2^32
+    const int8_t *sp = d.spins[0];
+    const uint4 v = *reinterpret_cast<const uint4 *>(sp + s0);
+    const uint4 vy = *reinterpret_cast<const uint4 *>(sp + (gz * L + gyn) * L + gx0);
+    const uint4 vz = *reinterpret_cast<const uint4 *>(sp + (gzn * L + gy) * L + gx0);
+    const uint32_t ex = (uint8_t)sp[(gz * L + gy) * L + (gx0 + kBrick == L ? 0u : gx0 + kBrick)];
+    const uint32_t t = (uint32_t)*d.tdev, T = d.T;
+
+    // bonds (Sec. 2.1): one Philox call per site, words 0, 1, 2 of counter
+    // {s, t, 4, 0} for +x, +y, +z; bonds join equal spins (Ising) or values
+    uint32_t EX = 0u, EY = 0u, EZ = 0u, mk[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (uint32_t j = 0; j < 16u; ++j) {
+        uint32_t w0 = s0 + j, w1 = t, w2 = 4u, w3 = 0u;
+        philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
+        const uint32_t a = byte_of(v, j), e = j < 15u ? byte_of(v, j + 1u) : ex;
+        const uint32_t n = byte_of(vy, j), u = byte_of(vz, j);
+        const uint32_t bxj = (uint32_t)(a == e && w0 < T), byj = (uint32_t)(a == n && w1 < T);
+        const uint32_t bzj = (uint32_t)(a == u && w2 < T);
+        EX |= bxj << j;
+        EY |= byj << j;
+        EZ |= bzj << j;
+        mk[j >> 2] |= (bxj | (byj << 1) | (bzj << 2)) << (8u * (j & 3u));
+    }
+
+    // brick-local clusters: every site points at the start of its x-run,
+    // then the +y and +z bonds inside the brick join runs (one union per
+    // group of consecutive bonds between the same two runs)
+    const uint32_t EXi = EX & 0x7FFFu;
+    const uint32_t base = tid * kBrick;
+    s_ex[tid] = EXi;
+    {
+        uint32_t cur = base;
+#pragma unroll
+        for (uint32_t j = 0; j < 16u; ++j) {
+            if (j == 0u || !((EXi >> (j - 1u)) & 1u)) cur = base + j;
+            s_par[base + j] = cur;
+        }
+    }
+    __syncthreads();
+    if (y < 15u) {
+        const uint32_t E1 = s_ex[tid + 1u];
+        uint32_t R = EY & ~((EY << 1) & (EXi << 1) & (E1 << 1)) & 0xFFFFu;
+        while (R) {
+            const uint32_t j = (uint32_t)__ffs((int)R) - 1u;
+            R &= R - 1u;
+            lds_union(s_par, base + j, base + j + kBrick);
+        }
+    }
+    if (z < 15u) {
+        const uint32_t E1 = s_ex[tid + kBrick];
+        uint32_t R = EZ & ~((EZ << 1) & (EXi << 1) & (E1 << 1)) & 0xFFFFu;
+        while (R) {
+            const uint32_t j = (uint32_t)__ffs((int)R) - 1u;
+            R &= R - 1u;
+            lds_union(s_par, base + j, base + j + kBrick * kBrick);
+        }
+    }
+    __syncthreads();
+    // local component sizes in the high halves of the roots' words: one add
+    // per x-run (a run lies in one component)
+    uint32_t rt[16];
+#pragma unroll
+    for (uint32_t j = 0; j < 16u; ++j) rt[j] = lds_root(s_par, base + j);
+#pragma unroll
+    for (uint32_t j = 0; j < 16u; ++j) {
+        if (j != 0u && ((EXi >> (j - 1u)) & 1u)) continue;
+        const uint32_t rest = (~EXi >> j) | 0x8000u;  // bit i set: the run ends at j + i
+        const uint32_t len = (uint32_t)__ffs((int)rest);
+        atomicAdd(&s_par[rt[j]], len << 16);
+    }
+    __syncthreads();
+    // labels = the global index of the local root; a local root (bit 3 of
+    // its mask byte) keeps its component size in le_cnt
+    uint32_t lab[16];
+#pragma unroll
+    for (uint32_t j = 0; j < 16u; ++j) {
+        const uint32_t r = rt[j];
+        lab[j] = ((bz * kBrick + (r >> 8)) * L + by * kBrick + ((r >> 4) & 15u)) * L + bx * kBrick + (r & 15u);
+        if (r == base + j) {
+            mk[j >> 2] |= 8u << (8u * (j & 3u));
+            d.le_cnt[s0 + j] = lds_load(&s_par[r]) >> 16;
+        }
+    }
+    *reinterpret_cast<uint4 *>(d.le_mask + s0) = make_uint4(mk[0], mk[1], mk[2], mk[3]);
+    uint4 *lp = reinterpret_cast<uint4 *>(d.labels + s0);
+    lp[0] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
+    lp[1] = make_uint4(lab[4], lab[5], lab[6], lab[7]);
+    lp[2] = make_uint4(lab[8], lab[9], lab[10], lab[11]);
+    lp[3] = make_uint4(lab[12], lab[13], lab[14], lab[15]);
+}
+
+// Bonds across brick faces: one thread per site of the +x, +y and +z faces
+// of every brick (768 per brick); a bonded site joins the set of its
+// neighbour in the next brick.  Neighbouring face sites whose bonds join
+// the same two brick-local roots need one union.
+__global__ __launch_bounds__(256) void k_bunion3(Dev d) {
+    const uint32_t L = d.L, nb = L / kBrick, LL = L * L;
+    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t brick = gid / 768u, r = gid % 768u, f = r >> 8, i = r & 255u;
+    const uint32_t bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
+    const uint32_t lx = f == 0u ? 15u : (i & 15u);
+    const uint32_t ly = f == 1u ? 15u : (f == 0u ? (i & 15u) : (i >> 4));
+    const uint32_t lz = f == 2u ? 15u : (i >> 4);
+    const uint32_t gx = bx * kBrick + lx, gy = by * kBrick + ly, gz = bz * kBrick + lz;
+    const uint32_t s = (gz * L + gy) * L + gx;
+    const uint32_t nbr = f == 0u ? (gx + 1u == L ? s - gx : s + 1u)
+                       : f == 1u ? (gy + 1u == L ? s - gy * L : s + L)
+                                 : (gz + 1u == L ? s - gz * LL : s + LL);
+    const bool has = ((uint32_t)d.le_mask[s] >> f) & 1u;
+    const uint32_t a = has ? g_load(&d.labels[s]) : 0u, c = has ? g_load(&d.labels[nbr]) : 0u;
+    // the previous lane holds the previous site of the same face row
+    const uint32_t pa = __shfl_up(a, 1, 64), pc = __shfl_up(c, 1, 64);
+    const int ph = __shfl_up((int)has, 1, 64);
+    const bool dup = (threadIdx.x & 63u) != 0u && (i & 15u) != 0u && ph && pa == a && pc == c;
+    if (has && !dup) g_union(d.labels, a, c);
+}
+
+// Every local root points at its final root (reads only ancestors, so
+// concurrent rewrites by other threads are harmless); other sites still
+// point at their local root.
+__global__ __launch_bounds__(256) void k_bflat3(Dev d) {
+    const uint32_t N = (uint32_t)d.nsite;
+    for (uint32_t s = blockIdx.x * 256u + threadIdx.x; s < N; s += gridDim.x * 256u) {
+        if (!(d.le_mask[s] & 8u)) continue;
+        const uint32_t l = g_load(&d.labels[s]);
+        uint32_t r = l;
+        while (true) {
+            const uint32_t p = g_load(&d.labels[r]);
+            if (p == r) break;
+            r = p;
+        }
+        if (r != l) g_store(&d.labels[s], r);
+    }
+}
+
+// Final labels, new spins of the clusters (Sec. 2.4) at their roots, and
+// cluster sizes: every local root that is not its cluster's root adds its
+// component size to the root's.
+__global__ __launch_bounds__(256) void k_brelabel3(Dev d) {
+    const uint32_t N = (uint32_t)d.nsite, t = (uint32_t)*d.tdev;
+    for (uint32_t s = blockIdx.x * 256u + threadIdx.x; s < N; s += gridDim.x * 256u) {
+        const bool local_root = (d.le_mask[s] & 8u) != 0u;
+        const uint32_t l = d.labels[s];
+        const uint32_t r = local_root ? l : d.labels[l];
+        if (!local_root) d.labels[s] = r;
+        if (r == s)
+            d.le_rsp[s] = d.q ? potts_spin(s, t, d.q, d.seed_lo, d.seed_hi) : cluster_spin(s, t, d.seed_lo, d.seed_hi);
+        else if (local_root)
+            atomicAdd(&d.le_cnt[r], d.le_cnt[s]);
+    }
+}
+
+// Every site takes its cluster's new spin.
+__global__ __launch_bounds__(256) void k_bflip3(Dev d) {
+    const uint32_t N = (uint32_t)d.nsite;
+    for (uint32_t s = blockIdx.x * 256u + threadIdx.x; s < N; s += gridDim.x * 256u)
+        d.spins[0][s] = d.le_rsp[d.labels[s]];
+}
+
 inline uint32_t grid_cap(size_t n, uint32_t per, uint32_t cap) {
     size_t g = (n + per - 1) / per;
     return (uint32_t)(g < 1 ? 1 : g > cap ? cap : g);
@@ -301,12 +491,22 @@ hipError_t launch_le_stage(const Dev &d, int stage, hipStream_t s) {
     const bool cubic = d.dims == 3u;
     switch (stage) {
     case 0:
-        if (cubic)
+        if (d.brick) {
+            const uint32_t nb = d.L / kBrick;
+            k_brick3<<<nb * nb * nb, 256, 0, s>>>(d);
+        } else if (cubic) {
             k_le_bond3<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);
-        else
+        } else {
             k_le_bond<<<grid_cap(N / 2, 256, 65536), 256, 0, s>>>(d);
+        }
         break;
     case 1: {
+        if (d.brick) {
+            const uint32_t nb = d.L / kBrick;
+            k_bunion3<<<nb * nb * nb * 3u, 256, 0, s>>>(d);
+            k_bflat3<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);
+            break;
+        }
         Dev dd = d;
         void *args[] = {&dd};
         const void *fn = cubic ? reinterpret_cast<const void *>(k_le_label<3>)
@@ -314,6 +514,11 @@ hipError_t launch_le_stage(const Dev &d, int stage, hipStream_t s) {
         return hipLaunchCooperativeKernel(fn, dim3(d.le_grid), dim3(256), args, 0, s);
     }
     case 2:
+        if (d.brick) {
+            k_brelabel3<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);
+            k_bflip3<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);
+            break;
+        }
         k_le_roots<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);
         k_le_flip<<<(uint32_t)((N + kLeChunk - 1) / kLeChunk), 256, 0, s>>>(d);
         break;

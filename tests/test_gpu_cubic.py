@@ -1,4 +1,5 @@
-"""Simple cubic (L x L x L) sweeps through the C ABI, Ising and Potts, bit for
+"""Simple cubic (L x L x L) sweeps through the C ABI, Ising and Potts, on
+the 16^3-brick path (the default) and on the label-equivalence path, bit for
 bit against the cubic oracle: records, spins and canonical labels; at full
 size, properties that hold at any L."""
 import math
@@ -23,24 +24,32 @@ def _same_records(a, b, where):
     assert np.array_equal(a["hist_log2"], b["hist_log2"]), f"{where} hist_log2"
 
 
-def _cube(L, beta, seed, q=0, flags=0, **kw):
-    print(f"\n[case] cubic L={L} q={q} beta={beta} seed={seed} {kw}", flush=True)
-    return sw.Sim(L, beta, 1.0, seed, q=q, dims=3, flags=sw.SW_FLAG_LABEL_EQUIV | flags, **kw)
+PATHS = ["brick", "label_equivalence"]
+
+
+def _cube(L, beta, seed, q=0, flags=0, path="brick", **kw):
+    print(f"\n[case] cubic {path} L={L} q={q} beta={beta} seed={seed} {kw}", flush=True)
+    if path == "label_equivalence":
+        flags |= sw.SW_FLAG_LABEL_EQUIV
+    s = sw.Sim(L, beta, 1.0, seed, q=q, dims=3, flags=flags, **kw)
+    assert s.tile == (16 if path == "brick" else 0)
+    return s
 
 
 def _threshold(q, beta):
     return oracle.potts_threshold(beta, 1.0) if q else oracle.threshold(beta, 1.0)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("L", [16, 32, 48])
-def test_ising_matches_oracle(L):
+def test_ising_matches_oracle(L, path):
     seed, n = 700 + L, 8
     for beta in (0.0, 0.1, BETA_C3, 0.5):
         T = _threshold(0, beta)
         sp = oracle.cubic_init(L, seed, 0)
         ref = oracle.cubic_run(L, 1.0, T, 0, seed, 0, n - 1, sp)
         last, lab, _, dense = oracle.cubic_sweep(L, 1.0, T, 0, seed, n - 1, sp, dense=True)
-        with _cube(L, beta, seed, flags=sw.SW_FLAG_DENSE_HIST) as s:
+        with _cube(L, beta, seed, flags=sw.SW_FLAG_DENSE_HIST, path=path) as s:
             assert s.threshold == T and sw.lib().sw_sites(s.handle) == L ** 3
             s.sweep(3)
             s.sweep(n - 3)
@@ -52,16 +61,17 @@ def test_ising_matches_oracle(L):
             assert np.array_equal(s.cluster_hist(), dense)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("q", [2, 3, 5])
-@pytest.mark.parametrize("L", [16, 32])
-def test_potts_matches_oracle(q, L):
+@pytest.mark.parametrize("L", [16, 32, 48])
+def test_potts_matches_oracle(q, L, path):
     seed, n = 900 + q + L, 8
     for beta in (0.3, 0.5505, 1.5):
         T = _threshold(q, beta)
         sp = oracle.cubic_init(L, seed, q)
         ref = oracle.cubic_run(L, 1.0, T, q, seed, 0, n - 1, sp)
         last, lab, _ = oracle.cubic_sweep(L, 1.0, T, q, seed, n - 1, sp)
-        with _cube(L, beta, seed, q=q) as s:
+        with _cube(L, beta, seed, q=q, path=path) as s:
             assert s.threshold == T
             s.sweep(n)
             got = s.series(0, n)
@@ -71,14 +81,15 @@ def test_potts_matches_oracle(q, L):
             assert np.array_equal(s.labels(), lab)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("q", [0, 3])
-def test_cold_start_and_resume(q):
+def test_cold_start_and_resume(q, path):
     L, seed = 32, 41
     beta = BETA_C3 if q == 0 else 0.5505
     T = _threshold(q, beta)
     sp = oracle.cubic_init(L, seed, q, cold=True)
     ref = oracle.cubic_run(L, 1.0, T, q, seed, 0, 5, sp)
-    with _cube(L, beta, seed, q=q, init=sw.SW_INIT_COLD) as s:
+    with _cube(L, beta, seed, q=q, init=sw.SW_INIT_COLD, path=path) as s:
         assert np.all(s.spins() == (0 if q else 1))
         s.sweep(5)
         _same_records(s.series(0, 5), ref, "cold")
@@ -94,28 +105,30 @@ def test_cold_start_and_resume(q):
         assert np.array_equal(s.spins(), oracle.cubic_init(L, seed, q))
 
 
-def test_mid_size_bit_exact():
-    """L = 256 (16.8 M sites), two sweeps at the critical coupling."""
+@pytest.mark.parametrize("path", PATHS)
+def test_mid_size_bit_exact(path):
+    """L = 256 (16.8 M sites, 4096 bricks), two sweeps at the critical coupling."""
     L, seed = 256, 5
     T = _threshold(0, BETA_C3)
     sp = oracle.cubic_init(L, seed, 0)
     ref = oracle.cubic_run(L, 1.0, T, 0, seed, 0, 2, sp)
-    with _cube(L, BETA_C3, seed) as s:
+    with _cube(L, BETA_C3, seed, path=path) as s:
         s.sweep(2)
         _same_records(s.series(0, 2), ref, "L=256")
         assert np.array_equal(s.spins(), sp)
 
 
-def test_full_size_properties():
+@pytest.mark.parametrize("path", PATHS)
+def test_full_size_properties(path):
     """L = 512 (134 M sites): integer invariants at the critical coupling, and
     the high-temperature series <e_sum>/N = 3v + 12 v^3 (1 - v^2), v = tanh
     beta, at beta = 0.05 (one sweep already averages over 1.6e8 edges)."""
     L = 512
     N = L ** 3
-    with _cube(L, BETA_C3, 17) as s:
+    with _cube(L, BETA_C3, 17, path=path) as s:
         s.sweep(12)
         recs = s.series(0, 12)
-        assert s.label_passes > 0
+        assert s.label_passes > 0 or path == "brick"
         assert np.all(recs["e_sum"] % 4 == (3 * N) % 4) and np.all(recs["m_sum"] % 2 == N % 2)
         assert np.all(recs["hist_log2"].sum(axis=1) == recs["n_clusters"])
         assert np.all(recs["max_cluster"] <= N) and np.all(recs["sum_sq_sizes"] >= N)
@@ -124,7 +137,7 @@ def test_full_size_properties():
         assert int(sp.astype(np.int64).sum()) == int(recs["m_sum"][-1])
     beta = 0.05
     v = math.tanh(beta)
-    with _cube(L, beta, 18) as s:
+    with _cube(L, beta, 18, path=path) as s:
         s.sweep(6)
         e = s.series(1, 5)["e_sum"] / N
         want = 3 * v + 12 * v ** 3 * (1 - v * v)
@@ -134,8 +147,8 @@ def test_full_size_properties():
 
 def test_cubic_configuration_errors():
     cases = [
-        dict(dims=3, flags=0),                               # needs the label-equivalence path
-        dict(dims=3, flags=sw.SW_FLAG_LABEL_EQUIV, L=40),    # not a multiple of 16
+        dict(dims=3, flags=0, L=40),                         # not a multiple of 16
+        dict(dims=3, flags=sw.SW_FLAG_LABEL_EQUIV, L=40),
         dict(dims=3, flags=sw.SW_FLAG_LABEL_EQUIV, L=1632),  # L^3 would reach 2^32
         dict(dims=3, flags=sw.SW_FLAG_LABEL_EQUIV, L=8),
         dict(dims=4, flags=sw.SW_FLAG_LABEL_EQUIV),

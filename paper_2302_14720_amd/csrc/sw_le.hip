@@ -445,28 +445,22 @@ __global__ __launch_bounds__(256) void k_bflat3(Dev d) {
     }
 }
 
-// Final labels, new spins of the clusters (Sec. 2.4) at their roots, and
-// cluster sizes: every local root that is not its cluster's root adds its
-// component size to the root's.
+// Final labels, new spins (Sec. 2.4) and cluster sizes.  Every site draws
+// its cluster's spin from the cluster's root itself (the draw depends only
+// on the root, so no pass has to wait for the roots' draws), and every
+// local root that is not its cluster's root adds its component size to the
+// root's.
 __global__ __launch_bounds__(256) void k_brelabel3(Dev d) {
     const uint32_t N = (uint32_t)d.nsite, t = (uint32_t)*d.tdev;
+    int8_t *sp = d.spins[0];
     for (uint32_t s = blockIdx.x * 256u + threadIdx.x; s < N; s += gridDim.x * 256u) {
         const bool local_root = (d.le_mask[s] & 8u) != 0u;
         const uint32_t l = d.labels[s];
         const uint32_t r = local_root ? l : d.labels[l];
         if (!local_root) d.labels[s] = r;
-        if (r == s)
-            d.le_rsp[s] = d.q ? potts_spin(s, t, d.q, d.seed_lo, d.seed_hi) : cluster_spin(s, t, d.seed_lo, d.seed_hi);
-        else if (local_root)
-            atomicAdd(&d.le_cnt[r], d.le_cnt[s]);
+        sp[s] = d.q ? potts_spin(r, t, d.q, d.seed_lo, d.seed_hi) : cluster_spin(r, t, d.seed_lo, d.seed_hi);
+        if (local_root && r != s) atomicAdd(&d.le_cnt[r], d.le_cnt[s]);
     }
-}
-
-// Every site takes its cluster's new spin.
-__global__ __launch_bounds__(256) void k_bflip3(Dev d) {
-    const uint32_t N = (uint32_t)d.nsite;
-    for (uint32_t s = blockIdx.x * 256u + threadIdx.x; s < N; s += gridDim.x * 256u)
-        d.spins[0][s] = d.le_rsp[d.labels[s]];
 }
 
 inline uint32_t grid_cap(size_t n, uint32_t per, uint32_t cap) {
@@ -516,7 +510,6 @@ hipError_t launch_le_stage(const Dev &d, int stage, hipStream_t s) {
     case 2:
         if (d.brick) {
             k_brelabel3<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);
-            k_bflip3<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);
             break;
         }
         k_le_roots<<<grid_cap(N, 256, 65536), 256, 0, s>>>(d);

@@ -163,3 +163,25 @@ def test_cubic_configuration_errors():
         with pytest.raises(sw.SwError) as e:
             sw.sw_get_spins(s.handle, 16 * 16)
         assert e.value.code == sw.SW_ERANGE
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_largest_cubic_lattice(path):
+    """The largest cubic lattice the library accepts (L = 1616, N = 4.22e9
+    sites, just below 2^32): two sweeps; the record invariants; E and M
+    recomputed from the spins on the host."""
+    L = 1616
+    N = L ** 3
+    with _cube(L, BETA_C3, 29, path=path) as s:
+        s.sweep(2)
+        recs = s.series(0, 2)
+        sp = s.spins()
+    assert np.all(recs["e_sum"] % 4 == (3 * N) % 4) and np.all(recs["m_sum"] % 2 == N % 2)
+    assert np.all(recs["hist_log2"].sum(axis=1) == recs["n_clusters"])
+    assert np.all(recs["max_cluster"] <= N) and np.all(recs["sum_sq_sizes"] >= N)
+    assert int(sp.sum(dtype=np.int64)) == int(recs["m_sum"][-1])
+    g = sp.reshape(L, L, L)
+    e = 0
+    for ax in range(3):
+        e += int(np.sum(g * np.roll(g, -1, axis=ax), dtype=np.int64))
+    assert e == int(recs["e_sum"][-1])

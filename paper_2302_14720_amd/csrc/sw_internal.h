@@ -19,7 +19,12 @@
 // the final spin (0x01 = +1, 0xFF = -1) or 2 + k, a reference to node k of
 // the tile, resolved through the node tables of that sweep when the byte is
 // read next (by the next sweep's k_tile, or by k_resolve at the end of
-// every sw_sweep call).
+// every sw_sweep call).  The q-state Potts model runs the same kernels with
+// values 0..q-1 as final bytes and node codes from 4 (64-wide tiles, q <= 4)
+// or 8 (32-wide tiles).
+//
+// The simple cubic lattice, and the paper's label equivalence on either
+// lattice, keep 32-bit labels per site in global memory instead (sw_le.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -106,3 +106,23 @@ def test_server_job_bytes():
     assert sw.Server.job_bytes(100, 100) == 0
     assert sw.Server.job_bytes(128, 0) == 0
     assert sw.sw_last_error is not None
+
+
+def test_model_and_lattice_validation(lib):
+    """Potts and cubic configurations are checked on the host: tile widths,
+    lattice sides, q and dims ranges; workspaces grow with the sites."""
+    ok = lambda **kw: sw.sw_workspace_bytes_ex(sw.sw_config_init(kw.pop("L", 64), 0.5, 1.0, 1, **kw))
+    assert ok(q=3) > 0 and ok(q=3, tile=64) > 0 and ok(q=8, tile=32) > 0
+    assert ok(q=5, tile=64) == 0 and "32-wide" in sw.sw_last_error()
+    assert ok(q=1) == 0 and ok(q=9) == 0
+    assert ok(q=5, tile=64, flags=sw.SW_FLAG_LABEL_EQUIV) > 0  # tile unused there
+    # cubic: L a multiple of 16 in [16, 1616]; labels kept for every site
+    n16, n32 = ok(L=16, dims=3), ok(L=32, dims=3)
+    assert n16 > 16 ** 3 * 9 and n32 > 32 ** 3 * 9 and n32 > n16
+    assert ok(L=32, dims=3, flags=sw.SW_FLAG_LABEL_EQUIV) > 0
+    assert ok(L=1616, dims=3) > 1616 ** 3 * 9
+    for bad in (8, 24, 1632):
+        assert ok(L=bad, dims=3) == 0
+    assert ok(L=48, dims=2) == 0  # the square lattice needs multiples of 32
+    assert ok(L=64, dims=2) == ok(L=64, dims=0) > 0
+    assert ok(dims=1) == 0 and ok(dims=4) == 0

@@ -42,6 +42,20 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # bond words plus 1/TW of a call for the flip bits of its tile row.
 TILE_BYTES_PER_SITE = 2.0
 PHILOX_OPS = 60.0
+# Paths with 32-bit labels in HBM, algorithmic bytes per site and sweep.
+# Label equivalence: bonds 2 (spins in, mask out), label init 4, every pass
+# 9 (scan: mask 1 + label 4; analysis: label 4), roots 4, flip 6 (labels 4,
+# new spin 1 gathered, spin 1 out), statistics 5 (spin 1, label 4).
+# Cubic bricks: bricks 6 (spin 1 in, mask 1 and label 4 out), face unions
+# 27/16 (3/16 of the sites on a +face: mask 1, two labels 8), flatten 1
+# (mask), relabel 10 (mask 1, label 4 in and out, spin 1 out), statistics 5.
+LE_BYTES_FIXED, LE_BYTES_PER_PASS = 21.0, 9.0
+BRICK_BYTES_PER_SITE = 6.0 + 27.0 / 16.0 + 1.0 + 10.0 + 5.0
+
+
+def hbm_fields(rate: float, bytes_per_site: float) -> dict:
+    gbs = rate * bytes_per_site / 1e9
+    return {"algorithmic_bytes_per_site": bytes_per_site, "hbm_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
 
 
 def kernel_source_sha() -> str:
@@ -197,6 +211,7 @@ def cubic(args):
                                  f"hot start seed 13, 16^3 bricks",
                      "value": L ** 3 * args.cubic_steps / dt, "ms_per_step": dt * 1e3 / args.cubic_steps,
                      "sweeps": args.cubic_steps,
+                     "roofline": hbm_fields(L ** 3 * args.cubic_steps / dt, BRICK_BYTES_PER_SITE),
                      "kernel_ms": {"bricks": prof["tile"], "face_unions_and_flatten": prof["union"],
                                    "spins_and_sizes": prof["flatten"], "statistics": prof["roots"],
                                    "record": prof["record"]}}
@@ -275,6 +290,7 @@ def label_equivalence(args, tile_rate):
             res[name] = L * L * args.le_steps / dt
             if flags:
                 res["passes_last_sweep"] = s.label_passes
+                res["roofline"] = hbm_fields(res[name], LE_BYTES_FIXED + LE_BYTES_PER_PASS * s.label_passes)
             s.close()
         res["tile_over_label_equivalence"] = res["tile"] / res["label_equivalence"]
         out[f"L{L}_beta{beta:.4f}"] = res
@@ -292,6 +308,8 @@ def label_equivalence(args, tile_rate):
         dt = time.perf_counter() - t0
         rec = s.observables()
         out[f"potts_q3_L{L}"] = {"value": L * L * args.le_steps / dt, "passes_last_sweep": s.label_passes,
+                                 "roofline": hbm_fields(L * L * args.le_steps / dt,
+                                                        LE_BYTES_FIXED + LE_BYTES_PER_PASS * s.label_passes),
                                  # not an equilibrium value: the lattice is still relaxing from
                                  # its hot start after these few sweeps
                                  "energy_per_site_last_sweep": float(rec["energy"]) / (L * L),
@@ -312,6 +330,8 @@ def label_equivalence(args, tile_rate):
         dt = time.perf_counter() - t0
         key = f"{name}_L{Lc}"
         out[key] = {"value": Lc ** 3 * args.le_steps / dt, "sites": Lc ** 3, "beta": beta,
+                    "roofline": hbm_fields(Lc ** 3 * args.le_steps / dt,
+                                           LE_BYTES_FIXED + LE_BYTES_PER_PASS * s.label_passes),
                     "passes_last_sweep": s.label_passes, "sweeps_from_hot_start": 3 + args.le_steps}
         s.close()
         print(f"[bench] {key}: {out[key]}", file=sys.stderr, flush=True)

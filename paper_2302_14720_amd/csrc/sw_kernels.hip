@@ -491,27 +491,28 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     }
     __syncthreads();
 
-    // ---- cluster sizes.  A piece is the part of a run inside this lane's 16
-    // sites; every piece adds its length to the root of its run, and every
-    // run start is pointed at its root.
+    // ---- cluster sizes.  Every run start in this lane's 16 sites is pointed
+    // at its root and adds the whole run's length (read off the row's
+    // run-start mask; the run may go on into the next lanes' sites).
     uint32_t rootmask = 0u;
     {
-        const uint32_t pst = st | 1u;  // piece starts
-        const uint32_t nxt = pst | 0x10000u;
-        uint32_t m = pst;
+        const Row after = (Row)(B0 >> 1);  // bit x: a run starts at x + 1
+        uint32_t m = st;
         while (m) {
             const uint32_t i = (uint32_t)__ffs((int)m) - 1u;
             m &= m - 1u;
-            const bool is_rs = (st >> i) & 1u;
-            const uint32_t n = is_rs ? rowoff + 4u * (x0 + i) : rs0;
+            const uint32_t n = rowoff + 4u * (x0 + i);
             const uint32_t root = lds_root_b(s_par, n);
-            if (is_rs) {
-                if (root != n)
-                    __hip_atomic_store(word_at(s_par, n), root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                else
-                    rootmask |= 1u << i;
-            }
-            const uint32_t len = (uint32_t)__ffs((int)(nxt >> (i + 1u)));
+            if (root != n)
+                __hip_atomic_store(word_at(s_par, n), root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            else
+                rootmask |= 1u << i;
+            const Row nx = (Row)(after >> (x0 + i));  // bit j: the next run starts j + 1 sites on
+            uint32_t len;
+            if constexpr (TW == 64)
+                len = nx ? (uint32_t)__ffsll((unsigned long long)nx) : (uint32_t)TW - (x0 + i);
+            else
+                len = nx ? (uint32_t)__ffs((int)nx) : (uint32_t)TW - (x0 + i);
             __hip_atomic_fetch_add(word_at(s_par, root), len << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }

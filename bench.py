@@ -462,6 +462,14 @@ def main() -> int:
     else:
         roofline = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
                     "traffic": None, "kernel": dom, "kernel_ms": per_sweep[dom]}
+    # measured HBM bytes of every kernel of a sweep (committed counters of the
+    # current kernel source), against the 12 B/site stream model
+    cnt_all = load_counters(L)
+    sweep_hbm = None
+    if cnt_all and cnt_all.get("sweep_hbm_bytes_per_site"):
+        bps = cnt_all["sweep_hbm_bytes_per_site"]
+        sweep_hbm = {"measured_bytes_per_site": bps, "model_bytes_per_site": 12.0,
+                     "GBs": value * bps / 1e9, "frac": value * bps / 1e9 / HBM_PEAK_GBS}
 
     out = {
         "metric": METRIC,
@@ -483,6 +491,7 @@ def main() -> int:
         },
         # site-updates/s x 12 B (the classic bond/label/flip stream model) / 8 TB/s
         "effective_roofline_12B_frac": value * 12.0 / (HBM_PEAK_GBS * 1e9),
+        "sweep_hbm": sweep_hbm,
         "roofline": roofline,
         "kernel_ms": prof,
         "cold_start": {"sweeps": args.cold_sweeps, "value": N * args.cold_sweeps / cdt,

@@ -1,12 +1,19 @@
-"""Python binding of libswmi.so -- Swendsen-Wang dynamics of the 2D Ising
-model on one MI355X (Protzman & Giedt, Sec. 2).
+"""Python binding of libswmi.so -- Swendsen-Wang dynamics on one MI355X
+(Protzman & Giedt, Sec. 2): the 2D Ising model, the q-state Potts model
+(``q=2..8``) and the simple cubic lattice (``dims=3``); batched replicas
+(``Batch``) and a job server (``Server``).
 
 The binding only marshals arguments: every step of a sweep runs in the HIP
 kernels of ``csrc/``.  Function names match the C ABI in ``include/swmi.h``;
 ``Sim`` is a thin object wrapper whose device workspace is a torch uint8
-tensor and whose stream is torch's current stream (torch provides memory and
+tensor and whose stream is a torch stream (torch provides memory and
 streams, nothing else).  If the library has not been built the first call
 raises -- there is no fallback implementation.
+
+    sim = Sim(1024, 0.4406868, seed=1)           # 2D Ising, hot start
+    sim.sweep(100); rec = sim.observables()      # energy, magnetisation, clusters
+    potts = Sim(1024, 1.0050525, q=3)            # 2D q = 3 Potts at ln(1 + sqrt 3)
+    cube = Sim(128, 0.2216544, dims=3)           # 3D Ising on 128^3 sites
 """
 from __future__ import annotations
 

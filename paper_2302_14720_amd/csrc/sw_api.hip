@@ -133,6 +133,10 @@ Layout layout_of(const sw_config &c) {
     o.le_cnt = le ? take(N * 4) : 0;
     o.le_rsp = le ? take(N) : 0;
     o.le_ctl = le ? take(64) : 0;
+    // cubic bricks: the x-face labels of every brick, so that the face
+    // unions read them contiguously
+    const bool brick = c.dims == 3 && !(c.flags & SW_FLAG_LABEL_EQUIV);
+    o.bface = brick ? take(N / 4096 * 512 * 4) : 0;
     o.total = off;
     return o;
 }
@@ -181,6 +185,7 @@ Dev make_dev(const sw_config &c, char *base, const Layout &lo) {
         if (c.dims == 3 && !(c.flags & SW_FLAG_LABEL_EQUIV)) {
             d.brick = 1u;
             d.tw = swmi::kBrick;
+            d.bface = (uint32_t *)(base + lo.bface);
         }
         d.le_mask = (uint8_t *)(base + lo.le_mask);
         d.le_cnt = (uint32_t *)(base + lo.le_cnt);

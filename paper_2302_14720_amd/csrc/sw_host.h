@@ -25,7 +25,7 @@ uint32_t bond_threshold(double beta, double J);
 
 struct Layout {
     size_t spins[2], parent[2], nk[2], key, nsize, rspin, edge, xb, tpart, gpart, acc, tdev, ring, labels,
-        dense, le_mask, le_cnt, le_rsp, le_ctl, total;
+        dense, le_mask, le_cnt, le_rsp, le_ctl, bface, total;
 };
 
 int resolve_tile(const sw_config &c);

@@ -71,6 +71,8 @@ struct Dev {
     uint32_t *le_cnt;     // [N] cluster size at each root
     int8_t *le_rsp;       // [N] new spin, valid at roots
     uint32_t *le_ctl;     // [8] pass flags (3), passes of the last sweep, status
+    uint32_t *bface;      // cubic bricks: [nbricks][2][256] labels of the x = 15 sites
+                          // (kMapNone unless bonded to +x) and of the x = 0 sites
     uint32_t L, tw, ntx, ntiles, ngroups;
     uint32_t T, seed_lo, seed_hi;
     uint32_t ring_cap;

@@ -394,6 +394,9 @@ __global__ __launch_bounds__(256) void k_brick3(Dev d) {
         }
     }
     *reinterpret_cast<uint4 *>(d.le_mask + s0) = make_uint4(mk[0], mk[1], mk[2], mk[3]);
+    uint32_t *bf = d.bface + (size_t)b * 512u;
+    bf[tid] = ((EX >> 15) & 1u) ? lab[15] : kMapNone;
+    bf[256u + tid] = lab[0];
     uint4 *lp = reinterpret_cast<uint4 *>(d.labels + s0);
     lp[0] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
     lp[1] = make_uint4(lab[4], lab[5], lab[6], lab[7]);
@@ -418,8 +421,20 @@ __global__ __launch_bounds__(256) void k_bunion3(Dev d) {
     const uint32_t nbr = f == 0u ? (gx + 1u == L ? s - gx : s + 1u)
                        : f == 1u ? (gy + 1u == L ? s - gy * L : s + L)
                                  : (gz + 1u == L ? s - gz * LL : s + LL);
-    const bool has = ((uint32_t)d.le_mask[s] >> f) & 1u;
-    const uint32_t a = has ? g_load(&d.labels[s]) : 0u, c = has ? g_load(&d.labels[nbr]) : 0u;
+    bool has;
+    uint32_t a, c;
+    if (f == 0u) {  // x faces: their sites are L apart, so read the brick's face records
+        const uint32_t nbk = (bz * nb + by) * nb + (bx + 1u == nb ? 0u : bx + 1u);
+        a = d.bface[(size_t)brick * 512u + i];
+        has = a != kMapNone;
+        c = has ? d.bface[(size_t)nbk * 512u + 256u + i] : 0u;
+        if (!has) a = 0u;
+        (void)nbr;
+    } else {
+        has = ((uint32_t)d.le_mask[s] >> f) & 1u;
+        a = has ? g_load(&d.labels[s]) : 0u;
+        c = has ? g_load(&d.labels[nbr]) : 0u;
+    }
     // the previous lane holds the previous site of the same face row
     const uint32_t pa = __shfl_up(a, 1, 64), pc = __shfl_up(c, 1, 64);
     const int ph = __shfl_up((int)has, 1, 64);

@@ -188,6 +188,34 @@ def potts_tile(args):
 
 CUBIC_WORKLOADS = (("ising", 0, 0.2216544), ("potts_q3", 3, 0.5505))
 
+# The paper's own SW timing experiment (its Sec. 5 table): 10^4 sweeps at
+# k_B T = 2.5 (beta = 0.4 with J = 1) for L = 128 .. 4096, GPU minutes on its
+# Tesla P100.  Context only: other hardware, other code.
+PAPER_SW_GPU_MINUTES = {128: 0.112, 256: 0.151, 512: 0.390, 1024: 1.472, 2048: 5.483, 4096: 22.440}
+
+
+def paper_table(args):
+    """The paper's timing experiment re-run here: 10^4 sweeps (by default) at
+    beta = 0.4 from a hot start for each lattice side of its table."""
+    import paper_2302_14720_amd as sw
+
+    out = {"sweeps": args.paper_sweeps, "beta": 0.4, "unit": "minutes", "rows": []}
+    for L, paper_min in PAPER_SW_GPU_MINUTES.items():
+        s = sw.Sim(L, 0.4, 1.0, 2500 + L)
+        s.sweep(5)
+        s.sync()
+        t0 = time.perf_counter()
+        s.sweep(args.paper_sweeps)
+        s.sync()
+        dt = time.perf_counter() - t0
+        s.close()
+        minutes = dt / 60.0 * 1e4 / args.paper_sweeps  # scaled to the table's 10^4 sweeps
+        out["rows"].append({"L": L, "minutes_per_1e4_sweeps": minutes, "site_updates_per_s": L * L * args.paper_sweeps / dt,
+                            "paper_p100_minutes": paper_min, "ratio_to_paper": paper_min / minutes})
+        print(f"[bench] paper table L={L}: {minutes:.4f} min per 10^4 sweeps (paper on P100: {paper_min} min)",
+              file=sys.stderr, flush=True)
+    return out
+
 
 def cubic(args):
     """The simple cubic lattice on 16^3 bricks (the default 3D path): 3D
@@ -365,6 +393,8 @@ def main() -> int:
                     help="timed sweeps of the q = 3 Potts model on the tile path (0 = skip)")
     ap.add_argument("--cubic-steps", type=int, default=20,
                     help="timed sweeps of the simple cubic lattice on 16^3 bricks (0 = skip)")
+    ap.add_argument("--paper-sweeps", type=int, default=10000,
+                    help="sweeps per lattice of the paper's timing table, L = 128..4096 at beta = 0.4 (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for "
                          "HBM byte counters)")
@@ -501,6 +531,7 @@ def main() -> int:
         "serving": serving(args) if args.serve_jobs > 0 else None,
         "potts_tile": potts_tile(args) if args.potts_steps > 0 else None,
         "cubic": cubic(args) if args.cubic_steps > 0 else None,
+        "paper_table": paper_table(args) if args.paper_sweeps > 0 else None,
         "label_equivalence": label_equivalence(args, value) if args.le_steps > 0 else None,
     }
     if not args.no_cpu_baseline:

@@ -268,6 +268,18 @@ int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const doubl
                     const uint64_t *seed, int32_t init, int64_t ring, int32_t tile,
                     void *dev_workspace, size_t ws_bytes, void *hip_stream, sw_batch **out);
 
+/* Batches of q-state Potts replicas (the model of sw_config.q): as
+ * sw_batch_workspace_bytes / sw_batch_create, with q[0..n-1] the q (2..8)
+ * of every replica.  tile 0 selects 64-wide tiles when every L is a
+ * multiple of 64 and every q is at most 4, else 32-wide; tile 64 with a q
+ * above 4 is SW_EINVAL.  Every replica's bits are those of a plain Potts
+ * sim with the same parameters. */
+size_t sw_batch_workspace_bytes_potts(int32_t n, const int32_t *L, const int32_t *q, int64_t ring,
+                                      int32_t tile);
+int sw_batch_create_potts(int32_t n, const int32_t *L, const double *beta, const double *J,
+                          const uint64_t *seed, const int32_t *q, int32_t init, int64_t ring, int32_t tile,
+                          void *dev_workspace, size_t ws_bytes, void *hip_stream, sw_batch **out);
+
 /* Re-initialises every replica (SW_INIT_HOT / SW_INIT_COLD) and sets t = 0. */
 int sw_batch_reset(sw_batch *batch, int32_t init_mode);
 

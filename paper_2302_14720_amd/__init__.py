@@ -111,6 +111,9 @@ _SIGNATURES = {
     "sw_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32]),
     "sw_batch_create": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64,
                                        ctypes.c_int32, _P, ctypes.c_size_t, _P, _P]),
+    "sw_batch_workspace_bytes_potts": (ctypes.c_size_t, [ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int32]),
+    "sw_batch_create_potts": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64,
+                                             ctypes.c_int32, _P, ctypes.c_size_t, _P, _P]),
     "sw_batch_reset": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sw_batch_sweep": (ctypes.c_int, [_P, ctypes.c_int64]),
     "sw_batch_sync": (ctypes.c_int, [_P]),
@@ -284,17 +287,27 @@ def _replica_arrays(L, beta, J, seed):
     return n, La, ba, Ja, sa
 
 
-def sw_batch_workspace_bytes(L, ring: int = 0, tile: int = 0) -> int:
+def sw_batch_workspace_bytes(L, ring: int = 0, tile: int = 0, q=None) -> int:
     La = np.ascontiguousarray(L, dtype=np.int32)
+    if q is not None:
+        qa = np.ascontiguousarray(np.broadcast_to(np.asarray(q, dtype=np.int32), (La.size,)))
+        return int(lib().sw_batch_workspace_bytes_potts(La.size, _ptr(La), _ptr(qa), ring, tile))
     return int(lib().sw_batch_workspace_bytes(La.size, _ptr(La), ring, tile))
 
 
 def sw_batch_create(L, beta, J, seed, init: int = SW_INIT_HOT, ring: int = 0, tile: int = 0, ws_ptr: int = 0,
-                    ws_bytes: int = 0, stream_ptr: int = 0) -> int:
+                    ws_bytes: int = 0, stream_ptr: int = 0, q=None) -> int:
+    """q: None for Ising replicas (sw_batch_create), else the Potts q of every
+    replica (sw_batch_create_potts)."""
     n, La, ba, Ja, sa = _replica_arrays(L, beta, J, seed)
     h = ctypes.c_void_p()
-    _check(lib().sw_batch_create(n, _ptr(La), _ptr(ba), _ptr(Ja), _ptr(sa), init, ring, tile, ws_ptr or None,
-                                 ws_bytes, stream_ptr or None, ctypes.byref(h)))
+    if q is not None:
+        qa = np.ascontiguousarray(np.broadcast_to(np.asarray(q, dtype=np.int32), (n,)))
+        _check(lib().sw_batch_create_potts(n, _ptr(La), _ptr(ba), _ptr(Ja), _ptr(sa), _ptr(qa), init, ring, tile,
+                                           ws_ptr or None, ws_bytes, stream_ptr or None, ctypes.byref(h)))
+    else:
+        _check(lib().sw_batch_create(n, _ptr(La), _ptr(ba), _ptr(Ja), _ptr(sa), init, ring, tile, ws_ptr or None,
+                                     ws_bytes, stream_ptr or None, ctypes.byref(h)))
     return h.value
 
 
@@ -433,22 +446,25 @@ class Batch:
     the same length."""
 
     def __init__(self, L, beta, J=1.0, seed=0, *, init: int = SW_INIT_HOT, ring: int = 0, tile: int = 0,
-                 device=None):
+                 q=None, device=None):
+        """q: None for Ising replicas, else the Potts q of every replica
+        (a scalar or a sequence)."""
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("Batch needs a ROCm GPU (torch.cuda.is_available() is False)")
         n, La, ba, Ja, sa = _replica_arrays(L, beta, J, seed)
         self.L = La.tolist()
-        nbytes = sw_batch_workspace_bytes(La, ring, tile)
+        self.q = q
+        nbytes = sw_batch_workspace_bytes(La, ring, tile, q=q)
         if nbytes == 0:
-            self.handle = sw_batch_create(La, ba, Ja, sa, init, ring, tile)  # raises with the reason
+            self.handle = sw_batch_create(La, ba, Ja, sa, init, ring, tile, q=q)  # raises with the reason
         dev = torch.device("cuda" if device is None else device)
         self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self._stream = torch.cuda.Stream(device=dev)
         torch.cuda.current_stream(dev).synchronize()
         self.handle = sw_batch_create(La, ba, Ja, sa, init, ring, tile, self._ws.data_ptr(), nbytes,
-                                      self._stream.cuda_stream)
+                                      self._stream.cuda_stream, q=q)
 
     def __len__(self) -> int:
         return len(self.L)

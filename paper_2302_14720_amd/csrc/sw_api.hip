@@ -606,6 +606,7 @@ namespace {
 constexpr int64_t kDefaultBatchRing = 1024;
 
 struct BatchPlan {
+    bool potts;
     std::vector<sw_config> cfg;
     std::vector<size_t> base;  // workspace offset of every replica
     size_t devs, tmap, wmap, gmap, umap, rmap, total;
@@ -614,17 +615,25 @@ struct BatchPlan {
 
 // Validates the replica table and lays out the batch workspace: the
 // replicas' buffers one after another, then the Dev table and the maps.
+// q: NULL for Ising replicas, else the Potts q (2..8) of every replica.
 int plan_batch(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
-               int32_t init, int64_t ring, int32_t tile, BatchPlan *p) {
+               const int32_t *q, int32_t init, int64_t ring, int32_t tile, BatchPlan *p) {
     if (n < 1 || n > swmi::kMaxReplicas)
         return fail(SW_EINVAL, "the number of replicas must be in [1, " + std::to_string(swmi::kMaxReplicas) + "]");
     if (!L || !beta || !J || !seed) return fail(SW_EINVAL, "replica arrays must not be NULL");
     if (init != SW_INIT_HOT && init != SW_INIT_COLD) return fail(SW_EINVAL, "init must be SW_INIT_HOT or SW_INIT_COLD");
     if (tile != 0 && tile != 32 && tile != 64) return fail(SW_EINVAL, "tile must be 0, 32 or 64");
-    bool all64 = true;
-    for (int32_t r = 0; r < n; ++r) all64 = all64 && (L[r] % 64 == 0);
+    bool all64 = true, small_q = true;
+    for (int32_t r = 0; r < n; ++r) {
+        all64 = all64 && (L[r] % 64 == 0);
+        if (q && (q[r] < 2 || q[r] > swmi::kMaxQ))
+            return fail(SW_EINVAL, "replica " + std::to_string(r) + ": Potts q must be in [2, 8]");
+        small_q = small_q && (!q || q[r] <= 4);
+    }
     if (tile == 64 && !all64) return fail(SW_EINVAL, "tile 64 needs every L to be a multiple of 64");
-    p->tw = tile != 0 ? (uint32_t)tile : all64 ? 64u : 32u;
+    if (tile == 64 && !small_q) return fail(SW_EINVAL, "tile 64 needs every Potts q to be at most 4");
+    p->potts = q != nullptr;
+    p->tw = tile != 0 ? (uint32_t)tile : (all64 && small_q) ? 64u : 32u;
     p->cfg.assign((size_t)n, sw_config{});
     p->base.assign((size_t)n, 0);
     size_t off = 0;
@@ -632,6 +641,7 @@ int plan_batch(int32_t n, const int32_t *L, const double *beta, const double *J,
     for (int32_t r = 0; r < n; ++r) {
         sw_config &c = p->cfg[(size_t)r];
         sw_config_init(&c, L[r], beta[r], J[r], seed[r]);
+        c.q = q ? q[r] : 0;
         c.init = init;
         c.tile = (int32_t)p->tw;
         c.ring = ring > 0 ? ring : kDefaultBatchRing;
@@ -711,26 +721,22 @@ int batch_check_replica(const sw_batch *b, int32_t r) {
     return SW_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t sw_batch_workspace_bytes(int32_t n, const int32_t *L, int64_t ring, int32_t tile) {
+size_t batch_bytes(int32_t n, const int32_t *L, const int32_t *q, int64_t ring, int32_t tile) {
     if (n < 1 || n > swmi::kMaxReplicas || !L) return 0;
     std::vector<double> beta((size_t)n, 0.0), J((size_t)n, 1.0);
     std::vector<uint64_t> seed((size_t)n, 0u);
     BatchPlan p;
-    if (plan_batch(n, L, beta.data(), J.data(), seed.data(), SW_INIT_HOT, ring, tile, &p) != SW_OK) return 0;
+    if (plan_batch(n, L, beta.data(), J.data(), seed.data(), q, SW_INIT_HOT, ring, tile, &p) != SW_OK) return 0;
     return p.total;
 }
 
-int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
-                    int32_t init, int64_t ring, int32_t tile, void *dev_workspace, size_t ws_bytes,
-                    void *hip_stream, sw_batch **out) {
+int batch_create(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
+                 const int32_t *q, int32_t init, int64_t ring, int32_t tile, void *dev_workspace, size_t ws_bytes,
+                 void *hip_stream, sw_batch **out) {
     if (!out) return fail(SW_EINVAL, "out is NULL");
     *out = nullptr;
     BatchPlan p;
-    int rc = plan_batch(n, L, beta, J, seed, init, ring, tile, &p);
+    int rc = plan_batch(n, L, beta, J, seed, q, init, ring, tile, &p);
     if (rc != SW_OK) return rc;
     if (dev_workspace && ws_bytes < p.total)
         return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes");
@@ -800,6 +806,7 @@ int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const doubl
     b->bd.nwmap = p.nwmap;
     b->bd.ngroups = p.ngroups;
     b->bd.tw = p.tw;
+    b->bd.potts = p.potts ? 1u : 0u;
 
     e = hipMemsetAsync(b->ws, 0, p.total, b->stream);
     if (e == hipSuccess)
@@ -829,6 +836,35 @@ int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const doubl
     }
     *out = b;
     return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sw_batch_workspace_bytes(int32_t n, const int32_t *L, int64_t ring, int32_t tile) {
+    return batch_bytes(n, L, nullptr, ring, tile);
+}
+
+size_t sw_batch_workspace_bytes_potts(int32_t n, const int32_t *L, const int32_t *q, int64_t ring, int32_t tile) {
+    if (!q) return 0;
+    return batch_bytes(n, L, q, ring, tile);
+}
+
+int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
+                    int32_t init, int64_t ring, int32_t tile, void *dev_workspace, size_t ws_bytes,
+                    void *hip_stream, sw_batch **out) {
+    return batch_create(n, L, beta, J, seed, nullptr, init, ring, tile, dev_workspace, ws_bytes, hip_stream, out);
+}
+
+int sw_batch_create_potts(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
+                          const int32_t *q, int32_t init, int64_t ring, int32_t tile, void *dev_workspace,
+                          size_t ws_bytes, void *hip_stream, sw_batch **out) {
+    if (!q) {
+        if (out) *out = nullptr;
+        return fail(SW_EINVAL, "q must not be NULL");
+    }
+    return batch_create(n, L, beta, J, seed, q, init, ring, tile, dev_workspace, ws_bytes, hip_stream, out);
 }
 
 int sw_batch_reset(sw_batch *b, int32_t init_mode) {

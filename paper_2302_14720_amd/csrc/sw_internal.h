@@ -108,6 +108,7 @@ struct BatchDev {
     const uint32_t *umap;  // [nugroups] one per kUG x kUG group of tiles (k_ulocal)
     const uint32_t *rmap;  // [n] the replicas (indices into devs) this launch covers
     uint32_t n, ntiles, nwmap, ngroups, nugroups, tw;
+    uint32_t potts;        // 1: every replica is a Potts model (q in its Dev)
 };
 
 // Paths with labels in global memory: stages 0..4 of a sweep (bonds and, for

@@ -729,10 +729,10 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
 // Batched launches run the same bodies over a table of replicas (map
 // entries replica << kMapShift | unit index), so every replica's bits are
 // those of its own plain sweep.
-template <int TW>
+template <int TW, bool POTTS = false>
 __global__ __launch_bounds__(TW *TW / 16) void k_tile_b(const Dev *devs, const uint32_t *map) {
     const uint32_t e = map[blockIdx.x];
-    tile_body<TW>(devs[e >> kMapShift], e & kMapMask);
+    tile_body<TW, POTTS>(devs[e >> kMapShift], e & kMapMask);
 }
 
 // =====================================================================
@@ -1394,10 +1394,10 @@ __global__ __launch_bounds__(TW *TW / 16) void k_resolve(Dev d) {
     resolve_body<TW, POTTS>(d, tile_of_block(blockIdx.x, d.ntiles));
 }
 
-template <int TW>
+template <int TW, bool POTTS = false>
 __global__ __launch_bounds__(TW *TW / 16) void k_resolve_b(const Dev *devs, const uint32_t *map) {
     const uint32_t e = map[blockIdx.x];
-    resolve_body<TW>(devs[e >> kMapShift], e & kMapMask);
+    resolve_body<TW, POTTS>(devs[e >> kMapShift], e & kMapMask);
 }
 
 // Initial spins (Fig. 1): hot = bit 0 of word 0 of Philox({s, 0, 2, 0}),
@@ -1520,7 +1520,11 @@ hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
     if (b.n == 0) return hipSuccess;
     switch (stage) {
     case 0:
-        if (b.tw == 64)
+        if (b.potts && b.tw == 64)
+            k_tile_b<64, true><<<b.ntiles, 256, 0, s>>>(b.devs, b.tmap);
+        else if (b.potts)
+            k_tile_b<32, true><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);
+        else if (b.tw == 64)
             k_tile_b<64><<<b.ntiles, 256, 0, s>>>(b.devs, b.tmap);
         else
             k_tile_b<32><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);
@@ -1559,7 +1563,11 @@ hipError_t launch_batch_sweep(const BatchDev &b, hipStream_t s) {
 
 hipError_t launch_batch_resolve(const BatchDev &b, hipStream_t s) {
     if (b.n == 0) return hipSuccess;
-    if (b.tw == 64)
+    if (b.potts && b.tw == 64)
+        k_resolve_b<64, true><<<b.ntiles, 256, 0, s>>>(b.devs, b.tmap);
+    else if (b.potts)
+        k_resolve_b<32, true><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);
+    else if (b.tw == 64)
         k_resolve_b<64><<<b.ntiles, 256, 0, s>>>(b.devs, b.tmap);
     else
         k_resolve_b<32><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);

@@ -126,3 +126,13 @@ def test_model_and_lattice_validation(lib):
     assert ok(L=48, dims=2) == 0  # the square lattice needs multiples of 32
     assert ok(L=64, dims=2) == ok(L=64, dims=0) > 0
     assert ok(dims=1) == 0 and ok(dims=4) == 0
+
+
+def test_potts_batch_workspace_validation(lib):
+    L = np.array([64, 128, 96], dtype=np.int32)
+    assert sw.sw_batch_workspace_bytes(L, q=[2, 3, 8]) > 0
+    assert sw.sw_batch_workspace_bytes(L, q=[2, 3, 9]) == 0
+    assert sw.sw_batch_workspace_bytes(L, q=[2, 1, 3]) == 0
+    assert sw.sw_batch_workspace_bytes(np.array([64, 128], dtype=np.int32), q=[3, 4], tile=64) > 0
+    assert sw.sw_batch_workspace_bytes(np.array([64, 128], dtype=np.int32), q=[3, 5], tile=64) == 0
+    assert lib.sw_batch_workspace_bytes_potts(2, L.ctypes.data_as(ctypes.c_void_p), None, 0, 0) == 0

@@ -149,3 +149,45 @@ def test_autotuner_picks_an_allowed_tile(tmp_path, monkeypatch):
         for r in range(3):
             _same_records(b1.series(r, 0, 6), b2.series(r, 0, 6), f"replica {r}")
             assert np.array_equal(b1.spins(r), b2.spins(r))
+
+
+@pytest.mark.parametrize("qs,L,want_tile", [
+    ([2, 3, 4, 3, 2], [64, 128, 192, 64, 256], 64),        # q <= 4, multiples of 64
+    ([3, 5, 8, 2], [64, 96, 128, 160], 32),                # q above 4 or L % 64 != 0
+])
+def test_potts_batch_matches_plain_and_oracle(qs, L, want_tile):
+    """A batch of Potts replicas (mixed q and L): every replica's records and
+    spins are those of a plain Potts sim, and for the small ones of the Potts
+    oracle."""
+    n = len(L)
+    beta = [math.log(1.0 + math.sqrt(q)) if i % 2 == 0 else 0.4 + 0.3 * i for i, q in enumerate(qs)]
+    seed = [600 + i for i in range(n)]
+    sweeps = 12
+    print(f"\n[case] Potts batch q={qs} L={L}", flush=True)
+    with sw.Batch(L, beta, 1.0, seed, q=qs) as b:
+        assert b.tile == want_tile
+        b.sweep(5)
+        b.sweep(sweeps - 5)
+        for r in range(n):
+            assert b.threshold(r) == oracle.potts_threshold(beta[r], 1.0)
+            got = b.series(r, 0, sweeps)
+            with sw.Sim(L[r], beta[r], 1.0, seed[r], q=qs[r], tile=want_tile) as s:
+                s.sweep(sweeps)
+                ref, sp = s.series(0, sweeps), s.spins()
+            _same_records(got, ref, f"replica {r}")
+            assert np.array_equal(b.spins(r), sp), f"replica {r} spins"
+            if L[r] <= 128:
+                osp = oracle.potts_init(L[r], seed[r], qs[r])
+                orec = oracle.potts_run(L[r], 1.0, oracle.potts_threshold(beta[r], 1.0), qs[r], seed[r], 0,
+                                        sweeps, osp)
+                _same_records(got, orec, f"replica {r} vs oracle")
+                assert np.array_equal(b.spins(r), osp)
+
+
+def test_potts_batch_errors():
+    with pytest.raises(sw.SwError) as e:
+        sw.Batch([64, 128], 0.5, 1.0, [1, 2], q=[3, 9])
+    assert e.value.code == sw.SW_EINVAL
+    with pytest.raises(sw.SwError) as e:
+        sw.Batch([64, 128], 0.5, 1.0, [1, 2], q=[3, 6], tile=64)
+    assert e.value.code == sw.SW_EINVAL

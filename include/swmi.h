@@ -335,8 +335,10 @@ typedef struct {
     uint64_t bytes;        /* device bytes the job holds while admitted       */
 } sw_job_info;
 
-/* Device bytes a job of side L running `sweeps` sweeps needs (0 if invalid). */
+/* Device bytes a job of side L running `sweeps` sweeps needs (0 if invalid);
+ * the _potts form for a q-state Potts job (q = 2..8). */
 size_t sw_server_job_bytes(int32_t L, int64_t sweeps);
+size_t sw_server_job_bytes_potts(int32_t L, int32_t q, int64_t sweeps);
 
 /* Creates a server with a device memory pool of pool_bytes: `pool` is a
  * 256-byte-aligned device buffer the caller keeps alive until
@@ -349,6 +351,12 @@ int sw_server_create(void *pool, size_t pool_bytes, int32_t max_jobs, void *hip_
  * sw_create_ex; sweeps >= 1.  SW_ENOMEM if the job can never fit the pool. */
 int sw_server_submit(sw_server *server, int32_t L, double beta, double J, uint64_t seed,
                      int32_t init, int64_t sweeps, int64_t *job_id);
+
+/* Queues a q-state Potts job (q = 2..8, the model of sw_config.q); Ising and
+ * Potts jobs share the pool and the steps, and each job's bits are those of
+ * a plain sim with the same parameters. */
+int sw_server_submit_potts(sw_server *server, int32_t L, double beta, double J, uint64_t seed, int32_t q,
+                           int32_t init, int64_t sweeps, int64_t *job_id);
 
 /* Admits queued jobs that fit, then runs up to n sweeps of the active set
  * (fewer if it empties), retiring jobs as they finish and admitting queued

@@ -127,9 +127,12 @@ _SIGNATURES = {
     "sw_batch_tile": (ctypes.c_int32, [_P]),
     "sw_batch_destroy": (None, [_P]),
     "sw_server_job_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
+    "sw_server_job_bytes_potts": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]),
     "sw_server_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.c_int32, _P, _P]),
     "sw_server_submit": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                                         ctypes.c_int32, ctypes.c_int64, _P]),
+    "sw_server_submit_potts": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P]),
     "sw_server_step": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_int32, _P]),
     "sw_server_job_info": (ctypes.c_int, [_P, ctypes.c_int64, _P]),
     "sw_server_job_series": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P]),
@@ -143,12 +146,20 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
-    """The loaded libswmi.so; raises if it has not been built."""
+    """The loaded libswmi.so; raises if it has not been built.
+
+    torch is imported first: its HIP and HSA runtime libraries carry the
+    sonames libswmi.so links against, so the library binds to the runtime
+    that owns torch's pointers and streams.  Loaded before torch it would
+    bring in a second HIP/HSA runtime, which finds no device once the first
+    has opened it, and to which torch's streams mean nothing."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        import torch  # noqa: F401  (one HIP runtime per process, torch's)
+
         l = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGNATURES.items():
             fn = getattr(l, name)
@@ -538,13 +549,19 @@ class Server:
         self._done_buf = np.zeros(4096, dtype=np.int64)
 
     @staticmethod
-    def job_bytes(L: int, sweeps: int) -> int:
+    def job_bytes(L: int, sweeps: int, q: int = 0) -> int:
+        if q:
+            return int(lib().sw_server_job_bytes_potts(L, q, sweeps))
         return int(lib().sw_server_job_bytes(L, sweeps))
 
     def submit(self, L: int, beta: float, J: float = 1.0, seed: int = 0, sweeps: int = 100,
-               init: int = SW_INIT_HOT) -> int:
+               init: int = SW_INIT_HOT, q: int = 0) -> int:
+        """q = 0: an Ising job; q = 2..8: a q-state Potts job."""
         jid = ctypes.c_int64()
-        _check(lib().sw_server_submit(self.handle, L, beta, J, seed, init, sweeps, ctypes.byref(jid)))
+        if q:
+            _check(lib().sw_server_submit_potts(self.handle, L, beta, J, seed, q, init, sweeps, ctypes.byref(jid)))
+        else:
+            _check(lib().sw_server_submit(self.handle, L, beta, J, seed, init, sweeps, ctypes.byref(jid)))
         return jid.value
 
     def step(self, n: int) -> list:

@@ -78,6 +78,17 @@ struct Pool {
     }
 };
 
+// Launch groups: Ising and Potts jobs, each with 64-wide or 32-wide tiles,
+// run different instantiations of the tile and resolve kernels.
+constexpr int kGroups = 4;
+int group_of(const Dev &d) { return (d.q ? 2 : 0) + (d.tw == 64 ? 0 : 1); }
+void set_groups(swmi::BatchDev *bd) {
+    for (int g = 0; g < kGroups; ++g) {
+        bd[g].tw = (g & 1) ? 32u : 64u;
+        bd[g].potts = g >= 2 ? 1u : 0u;
+    }
+}
+
 // Work maps of one launch group (see swmi::BatchDev), built on the host.
 struct Maps {
     std::vector<uint32_t> t, w, g, u, r;
@@ -118,7 +129,7 @@ struct sw_server {
     std::vector<Job *> active;
     int64_t next_id = 1;
     bool dirty = true;
-    swmi::BatchDev bd[2]{};  // active jobs with 64-wide and 32-wide tiles
+    swmi::BatchDev bd[kGroups]{};  // active jobs by launch group (see group_of)
     uint64_t site_updates = 0;
 };
 
@@ -131,7 +142,7 @@ int srv_device(const sw_server *s) {
     return SW_OK;
 }
 
-// Copies the maps of up to two launch groups into the device map buffer and
+// Copies the maps of the launch groups into the device map buffer and
 // points the BatchDevs at them.  The stream is idle when this runs.
 int upload_maps(sw_server *s, Maps *m, swmi::BatchDev *bd, int ngroups) {
     size_t need = 0;
@@ -180,11 +191,10 @@ int upload_maps(sw_server *s, Maps *m, swmi::BatchDev *bd, int ngroups) {
 
 int rebuild_active(sw_server *s) {
     HIP_TRY(hipStreamSynchronize(s->stream));
-    Maps m[2];
-    for (Job *j : s->active) m[j->dev.tw == 64 ? 0 : 1].add((uint32_t)j->slot, j->dev);
-    s->bd[0].tw = 64;
-    s->bd[1].tw = 32;
-    const int rc = upload_maps(s, m, s->bd, 2);
+    Maps m[kGroups];
+    for (Job *j : s->active) m[group_of(j->dev)].add((uint32_t)j->slot, j->dev);
+    set_groups(s->bd);
+    const int rc = upload_maps(s, m, s->bd, kGroups);
     if (rc == SW_OK) s->dirty = false;
     return rc;
 }
@@ -228,21 +238,42 @@ int find_job(sw_server *s, int64_t id, Job **out) {
     return SW_OK;
 }
 
-sw_config job_config(int32_t L, double beta, double J, uint64_t seed, int32_t init, int64_t sweeps) {
+sw_config job_config(int32_t L, double beta, double J, uint64_t seed, int32_t q, int32_t init, int64_t sweeps) {
     sw_config c;
     sw_config_init(&c, L, beta, J, seed);
+    c.q = q;
     c.init = init;
     c.ring = sweeps;
     return c;
+}
+
+int submit(sw_server *s, const sw_config &c, int64_t sweeps, int64_t *job_id) {
+    int rc = swmi::validate(&c);
+    if (rc != SW_OK) return rc;
+    const size_t bytes = swmi::align_up(swmi::layout_of(c).total);
+    if (bytes > s->pool.size)
+        return fail(SW_ENOMEM, "job needs " + std::to_string(bytes) + " bytes, more than the whole pool");
+    Job *j = new (std::nothrow) Job();
+    if (!j) return fail(SW_ENOMEM, "host allocation failed");
+    j->id = s->next_id++;
+    j->cfg = c;
+    j->bytes = bytes;
+    j->target = sweeps;
+    s->jobs[j->id] = j;
+    s->queue.push_back(j);
+    *job_id = j->id;
+    return SW_OK;
 }
 
 }  // namespace
 
 extern "C" {
 
-size_t sw_server_job_bytes(int32_t L, int64_t sweeps) {
+size_t sw_server_job_bytes(int32_t L, int64_t sweeps) { return sw_server_job_bytes_potts(L, 0, sweeps); }
+
+size_t sw_server_job_bytes_potts(int32_t L, int32_t q, int64_t sweeps) {
     if (sweeps < 1) return 0;
-    const sw_config c = job_config(L, 0.0, 1.0, 0, SW_INIT_HOT, sweeps);
+    const sw_config c = job_config(L, 0.0, 1.0, 0, q, SW_INIT_HOT, sweeps);
     if (swmi::validate(&c) != SW_OK) return 0;
     return swmi::align_up(swmi::layout_of(c).total);
 }
@@ -298,22 +329,15 @@ int sw_server_submit(sw_server *s, int32_t L, double beta, double J, uint64_t se
                      int64_t *job_id) {
     if (!s || !job_id) return fail(SW_EINVAL, "server or job_id is NULL");
     if (sweeps < 1) return fail(SW_EINVAL, "sweeps must be >= 1");
-    const sw_config c = job_config(L, beta, J, seed, init, sweeps);
-    int rc = swmi::validate(&c);
-    if (rc != SW_OK) return rc;
-    const size_t bytes = swmi::align_up(swmi::layout_of(c).total);
-    if (bytes > s->pool.size)
-        return fail(SW_ENOMEM, "job needs " + std::to_string(bytes) + " bytes, more than the whole pool");
-    Job *j = new (std::nothrow) Job();
-    if (!j) return fail(SW_ENOMEM, "host allocation failed");
-    j->id = s->next_id++;
-    j->cfg = c;
-    j->bytes = bytes;
-    j->target = sweeps;
-    s->jobs[j->id] = j;
-    s->queue.push_back(j);
-    *job_id = j->id;
-    return SW_OK;
+    return submit(s, job_config(L, beta, J, seed, 0, init, sweeps), sweeps, job_id);
+}
+
+int sw_server_submit_potts(sw_server *s, int32_t L, double beta, double J, uint64_t seed, int32_t q, int32_t init,
+                           int64_t sweeps, int64_t *job_id) {
+    if (!s || !job_id) return fail(SW_EINVAL, "server or job_id is NULL");
+    if (sweeps < 1) return fail(SW_EINVAL, "sweeps must be >= 1");
+    if (q < 2 || q > swmi::kMaxQ) return fail(SW_EINVAL, "Potts q must be in [2, 8]");
+    return submit(s, job_config(L, beta, J, seed, q, init, sweeps), sweeps, job_id);
 }
 
 int sw_server_step(sw_server *s, int64_t n, int64_t *done_ids, int32_t cap, int32_t *ndone) {
@@ -334,7 +358,7 @@ int sw_server_step(sw_server *s, int64_t n, int64_t *done_ids, int32_t cap, int3
         int64_t k = left;
         for (const Job *j : s->active) k = std::min(k, j->target - j->done);
         for (int64_t i = 0; i < k; ++i)
-            for (int g = 0; g < 2; ++g) HIP_TRY(swmi::launch_batch_sweep(s->bd[g], s->stream));
+            for (int g = 0; g < kGroups; ++g) HIP_TRY(swmi::launch_batch_sweep(s->bd[g], s->stream));
         uint64_t sites = 0;
         for (Job *j : s->active) {
             j->done += k;
@@ -348,14 +372,13 @@ int sw_server_step(sw_server *s, int64_t n, int64_t *done_ids, int32_t cap, int3
         for (Job *j : s->active) (j->done == j->target ? fin : keep).push_back(j);
         if (fin.empty()) continue;
         HIP_TRY(hipStreamSynchronize(s->stream));
-        Maps m[2];
-        swmi::BatchDev rb[2]{};
-        for (Job *j : fin) m[j->dev.tw == 64 ? 0 : 1].add((uint32_t)j->slot, j->dev);
-        rb[0].tw = 64;
-        rb[1].tw = 32;
-        rc = upload_maps(s, m, rb, 2);
+        Maps m[kGroups];
+        swmi::BatchDev rb[kGroups]{};
+        for (Job *j : fin) m[group_of(j->dev)].add((uint32_t)j->slot, j->dev);
+        set_groups(rb);
+        rc = upload_maps(s, m, rb, kGroups);
         if (rc != SW_OK) return rc;
-        for (int g = 0; g < 2; ++g) HIP_TRY(swmi::launch_batch_resolve(rb[g], s->stream));
+        for (int g = 0; g < kGroups; ++g) HIP_TRY(swmi::launch_batch_resolve(rb[g], s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
         for (Job *j : fin) {
             j->state = SW_JOB_DONE;

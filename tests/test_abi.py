@@ -108,6 +108,37 @@ def test_server_job_bytes():
     assert sw.sw_last_error is not None
 
 
+def test_server_potts_job_bytes():
+    assert sw.Server.job_bytes(128, 100, q=3) == sw.Server.job_bytes(128, 100) > 0  # same 64-wide tile layout
+    assert sw.Server.job_bytes(96, 100, q=5) > 0  # 32-wide tiles above q = 4
+    assert sw.Server.job_bytes(128, 100, q=1) == 0 and sw.Server.job_bytes(128, 100, q=9) == 0
+
+
+_RUNTIMES = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import paper_2302_14720_amd as sw
+sw.lib()
+import torch
+maps = {line.split()[-1] for line in open("/proc/self/maps") if "/" in line}
+for tag in ("libamdhip64", "libhsa-runtime64"):
+    print(tag, len([m for m in maps if tag in m.rsplit("/", 1)[-1]]))
+"""
+
+
+def test_library_shares_torch_hip_runtime(lib):
+    """Loading the library before anything else imports torch must still
+    leave one HIP and one HSA runtime in the process (torch's): a second
+    copy would not see the device torch holds, nor torch's streams."""
+    import subprocess
+    import sys
+
+    out = subprocess.run([sys.executable, "-c", _RUNTIMES, ROOT], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    counts = dict(line.split() for line in out.stdout.splitlines())
+    assert counts == {"libamdhip64": "1", "libhsa-runtime64": "1"}, out.stdout
+
+
 def test_model_and_lattice_validation(lib):
     """Potts and cubic configurations are checked on the host: tile widths,
     lattice sides, q and dims ranges; workspaces grow with the sites."""

@@ -130,3 +130,43 @@ def test_server_errors():
         srv.release(q)  # a queued job can be withdrawn
         _drain(srv)
         srv.release(j)
+
+
+def test_ising_and_potts_jobs_share_the_server():
+    """Ising jobs and q-state Potts jobs (64-wide tiles for q <= 4, 32-wide
+    above) in one pool: every job's records and spins are those of a plain
+    sim run alone, and for small lattices of the oracle."""
+    jobs = [  # L, beta, seed, sweeps, q
+        (64, BETA_C, 51, 11, 0),
+        (128, math.log(1.0 + math.sqrt(3.0)), 52, 14, 3),
+        (96, 0.9, 53, 9, 5),
+        (192, 1.2, 54, 7, 2),
+        (64, 1.5, 55, 13, 8),
+        (160, 0.4, 56, 6, 0),
+    ]
+    need = [sw.Server.job_bytes(L, n, q) for (L, _, _, n, q) in jobs]
+    assert all(x > 0 for x in need)
+    print(f"\n[case] server Ising + Potts jobs, pool={sum(need)}", flush=True)
+    with sw.Server(sum(sorted(need)[-4:]) + 4096, max_jobs=4) as srv:
+        ids = [srv.submit(L, b, 1.0, s, n, q=q) for (L, b, s, n, q) in jobs]
+        results = {}
+
+        def collect(jid):
+            info = srv.info(jid)
+            results[jid] = (srv.series(jid, 0, info["sweeps_done"]), srv.spins(jid))
+            srv.release(jid)
+
+        done = _drain(srv, 4, collect=collect)
+        assert sorted(done) == sorted(ids)
+    for jid, (L, b, s, n, q) in zip(ids, jobs):
+        got, spins = results[jid]
+        with sw.Sim(L, b, 1.0, s, q=q) as solo:
+            solo.sweep(n)
+            ref, sp = solo.series(0, n), solo.spins()
+        _same_records(got, ref, f"job L={L} q={q}")
+        assert np.array_equal(spins, sp)
+        if q and L <= 96:
+            osp = oracle.potts_init(L, s, q)
+            orec = oracle.potts_run(L, 1.0, oracle.potts_threshold(b, 1.0), q, s, 0, n, osp)
+            _same_records(got, orec, f"job L={L} q={q} vs oracle")
+            assert np.array_equal(spins, osp)

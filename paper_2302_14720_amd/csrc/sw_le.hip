@@ -478,6 +478,95 @@ __global__ __launch_bounds__(256) void k_brelabel3(Dev d) {
     }
 }
 
+// Brick path: the statistics of the new configuration and of the sweep's
+// clusters (those of k_le_stats, in the same group partials: workgroup b
+// covers sites [kLeChunk b, kLeChunk (b + 1)), one x-segment of 16 sites
+// per thread, whose spins and labels come in 16-byte loads; L is a multiple
+// of 16, so a segment lies in one row and L^3 is a multiple of kLeChunk).
+// Potts value populations are counted in registers, 16 bits per value, and
+// added once per wavefront.
+__global__ __launch_bounds__(256) void k_bstats3(Dev d) {
+    static_assert(kLeChunk == 256u * 16u, "one 16-site segment per thread");
+    __shared__ unsigned long long s_acc[GP_END];
+    __shared__ unsigned int s_cnt[kMaxQ];
+    for (uint32_t i = threadIdx.x; i < (uint32_t)GP_END; i += 256u) s_acc[i] = 0ull;
+    if (threadIdx.x < (uint32_t)kMaxQ) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint32_t L = d.L, LL = L * L;
+    const uint32_t s0 = blockIdx.x * kLeChunk + 16u * threadIdx.x;
+    const uint32_t x0 = s0 % L, yz = s0 / L, y = yz % L, z = yz / L;
+    const int8_t *sp = d.spins[0];
+    // +x, +y, +z neighbours of the segment (periodic)
+    const uint4 v = *reinterpret_cast<const uint4 *>(sp + s0);
+    const uint4 vy = *reinterpret_cast<const uint4 *>(sp + (y + 1u == L ? s0 - y * L : s0 + L));
+    const uint4 vz = *reinterpret_cast<const uint4 *>(sp + (z + 1u == L ? s0 - z * LL : s0 + LL));
+    const uint32_t vx = (uint8_t)sp[x0 + 16u == L ? s0 - x0 : s0 + 16u];
+    const uint4 *lp = reinterpret_cast<const uint4 *>(d.labels + s0);
+    const uint4 a0 = lp[0], a1 = lp[1], a2 = lp[2], a3 = lp[3];
+    const uint32_t lab[16] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
+                              a2.x, a2.y, a2.z, a2.w, a3.x, a3.y, a3.z, a3.w};
+    int32_t e = 0, m = 0;
+    uint64_t c01 = 0u, c23 = 0u;  // Potts populations of values 0-3 and 4-7
+#pragma unroll
+    for (uint32_t j = 0; j < 16u; ++j) {
+        const uint32_t bs = byte_of(v, j), bx = j < 15u ? byte_of(v, j + 1u) : vx;
+        const uint32_t by = byte_of(vy, j), bz = byte_of(vz, j);
+        if (d.q) {
+            e += (int32_t)(bs == bx) + (int32_t)(bs == by) + (int32_t)(bs == bz);
+            const uint64_t one = 1ull << (16u * (bs & 3u));
+            if (bs < 4u)
+                c01 += one;
+            else
+                c23 += one;
+        } else {
+            const int32_t si = (int8_t)bs;
+            e += si * ((int8_t)bx + (int8_t)by + (int8_t)bz);
+            m += si;
+        }
+    }
+    uint64_t n = 0, mx = 0, sq = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 16u; ++j) {
+        if (lab[j] != s0 + j) continue;
+        const uint32_t S = d.le_cnt[s0 + j];
+        ++n;
+        mx = max(mx, (uint64_t)S);
+        sq += (uint64_t)S * S;
+        atomicAdd(&s_acc[GP_HIST + (31 - __clz((int)max(S, 1u)))], 1ull);
+        if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
+    }
+    int64_t e64 = e, m64 = m;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        e64 += __shfl_xor(e64, o, 64);
+        m64 += __shfl_xor(m64, o, 64);
+        n += __shfl_xor(n, o, 64);
+        mx = max(mx, (uint64_t)__shfl_xor((unsigned long long)mx, o, 64));
+        sq += __shfl_xor(sq, o, 64);
+        c01 += __shfl_xor(c01, o, 64);  // at most 64 * 16 per value: no carry between fields
+        c23 += __shfl_xor(c23, o, 64);
+    }
+    if ((threadIdx.x & 63u) == 0u) {
+        atomicAdd(&s_acc[GP_E], (unsigned long long)e64);
+        atomicAdd(&s_acc[GP_M], (unsigned long long)m64);
+        atomicAdd(&s_acc[GP_N], (unsigned long long)n);
+        atomicMax(&s_acc[GP_MAX], (unsigned long long)mx);
+        atomicAdd(&s_acc[GP_SQ], (unsigned long long)sq);
+        if (d.q) {
+#pragma unroll
+            for (uint32_t k = 0; k < 4u; ++k) {
+                atomicAdd(&s_cnt[k], (unsigned int)((c01 >> (16u * k)) & 0xFFFFu));
+                if (4u + k < (uint32_t)kMaxQ) atomicAdd(&s_cnt[4u + k], (unsigned int)((c23 >> (16u * k)) & 0xFFFFu));
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < (uint32_t)kMaxQ) s_acc[GP_CNT + threadIdx.x] = s_cnt[threadIdx.x];
+    __syncthreads();
+    uint64_t *gp = d.gpart + (size_t)blockIdx.x * kGroupPart;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)GP_END; i += 256u) gp[i] = s_acc[i];
+}
+
 inline uint32_t grid_cap(size_t n, uint32_t per, uint32_t cap) {
     size_t g = (n + per - 1) / per;
     return (uint32_t)(g < 1 ? 1 : g > cap ? cap : g);
@@ -531,6 +620,10 @@ hipError_t launch_le_stage(const Dev &d, int stage, hipStream_t s) {
         k_le_flip<<<(uint32_t)((N + kLeChunk - 1) / kLeChunk), 256, 0, s>>>(d);
         break;
     case 3:
+        if (d.brick) {
+            k_bstats3<<<(uint32_t)(N / kLeChunk), 256, 0, s>>>(d);
+            break;
+        }
         k_le_stats<<<(uint32_t)((N + kLeChunk - 1) / kLeChunk), 256, 0, s>>>(d);
         break;
     default:

@@ -31,10 +31,11 @@ BETA_C = math.log(1.0 + math.sqrt(2.0)) / 2.0
 
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
-# Integer VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one
-# 32-bit integer op per lane per clock; packed math does not apply to the
-# integer multiplies and xors that dominate here).
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Integer VALU peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 Tops/s,
+# one 32-bit op per lane per clock: the lane rate behind the published
+# 157.3 TFLOP/s FP32 vector peak (an FMA is two flops).  A wave64 VALU
+# instruction takes a SIMD two clocks.
+ALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 
 # Algorithmic work of k_tile per site.  Bytes: the spin byte read and the
 # spin byte written.  Integer ops: Philox4x32-10 costs 10 rounds x (2 wide
@@ -78,8 +79,8 @@ def load_counters(L: int):
     return d
 
 
-# VALU issue ceiling: one wave64 instruction per SIMD every 4 cycles
-VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+# VALU issue ceiling: one wave64 instruction per SIMD every 2 clocks
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2
 
 
 def cpu_baseline(L: int, seed: int):

@@ -209,3 +209,26 @@ def test_L4096_one_step(cold):
     rrec, _, _ = oracle.sweep(L, 1.0, T, seed, 3, state)
     assert np.array_equal(got, state)
     assert rec.tobytes() == rrec.tobytes()
+
+
+@pytest.mark.parametrize("L,tile,q", [(128, 64, 0), (96, 32, 0), (128, 64, 3), (96, 32, 5)])
+def test_profile_runs_the_same_sweeps(L, tile, q):
+    """sw_profile launches the sweep's five stages one by one with events
+    between them: the sweeps it runs are those of sw_sweep, bit for bit,
+    mixed with ordinary sweeps; every stage reports a time."""
+    seed, n = 31 + L + q, 9
+    beta = BETA_C if q == 0 else 1.0
+    if q:
+        sp = oracle.potts_init(L, seed, q)
+        ref = oracle.potts_run(L, 1.0, oracle.potts_threshold(beta, 1.0), q, seed, 0, n, sp)
+    else:
+        ref, sp = _oracle_run(L, beta, seed, n)
+    with _sim(L, beta, seed, tile=tile, q=q) as s:
+        s.sweep(2)
+        prof = s.profile(4)
+        s.sweep(n - 6)
+        assert set(prof) == set(sw.PROFILE_STAGES) and len(sw.PROFILE_STAGES) == 6
+        assert all(math.isfinite(v) and v >= 0.0 for v in prof.values())
+        assert prof["tile"] > 0.0 and prof["record"] > 0.0
+        _assert_records(s.series(0, n), ref, f"profiled L={L} tile={tile} q={q}")
+        assert np.array_equal(s.spins(), sp)

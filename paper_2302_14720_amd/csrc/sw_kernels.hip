@@ -497,6 +497,9 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     uint32_t rootmask = 0u;
     {
         const Row after = (Row)(B0 >> 1);  // bit x: a run starts at x + 1
+        // lengths of consecutive runs with the same root are summed in a
+        // register (at most TW per lane) and added with one atomic
+        uint32_t acc_root = 0u, acc_len = 0u;
         uint32_t m = st;
         while (m) {
             const uint32_t i = (uint32_t)__ffs((int)m) - 1u;
@@ -513,8 +516,15 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
                 len = nx ? (uint32_t)__ffsll((unsigned long long)nx) : (uint32_t)TW - (x0 + i);
             else
                 len = nx ? (uint32_t)__ffs((int)nx) : (uint32_t)TW - (x0 + i);
-            __hip_atomic_fetch_add(word_at(s_par, root), len << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (root != acc_root && acc_len != 0u)
+                __hip_atomic_fetch_add(word_at(s_par, acc_root), acc_len << 16, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            acc_len = root != acc_root ? len : acc_len + len;
+            acc_root = root;
         }
+        if (acc_len != 0u)
+            __hip_atomic_fetch_add(word_at(s_par, acc_root), acc_len << 16, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
 

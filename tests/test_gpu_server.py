@@ -126,6 +126,19 @@ def test_server_errors():
         with pytest.raises(sw.SwError) as e:
             srv.series(j, 0, 4)
         assert e.value.code == sw.SW_ERANGE
+        for bad_q in (1, 9, -3):  # Potts q outside [2, 8]
+            with pytest.raises(sw.SwError) as e:
+                srv.submit(64, 1.0, 1.0, 1, 10, q=bad_q)
+            assert e.value.code == sw.SW_EINVAL and "q" in str(e.value)
+        with pytest.raises(sw.SwError) as e:
+            srv.submit(100, 1.0, 1.0, 1, 10, q=5)  # not a multiple of 32
+        assert e.value.code == sw.SW_EINVAL
+        with pytest.raises(sw.SwError) as e:
+            srv.submit(4096, 1.0, 1.0, 1, 10, q=3)  # larger than the whole pool
+        assert e.value.code == sw.SW_ENOMEM
+        with pytest.raises(sw.SwError) as e:
+            srv.submit(64, 1.0, 1.0, 1, 0, q=3)
+        assert e.value.code == sw.SW_EINVAL
         q = srv.submit(64, 0.4, 1.0, 2, 10)
         srv.release(q)  # a queued job can be withdrawn
         _drain(srv)

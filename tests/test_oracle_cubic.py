@@ -97,6 +97,23 @@ def test_beta_zero_every_site_its_own_cluster(q):
     assert rec["n_clusters"] == n and rec["max_cluster"] == 1 and dense[1] == n
 
 
+@pytest.mark.parametrize("q", [3, 5])
+def test_potts_m_sum_is_the_largest_population(q):
+    """Potts records (R14, R15): m_sum is the population of the most
+    populated value, recounted here from the returned spins; a high
+    temperature keeps every value the largest now and then."""
+    L = 6
+    T = oracle.potts_threshold(0.2)
+    sp = oracle.cubic_init(L, 41, q)
+    winners = set()
+    for t in range(40):
+        rec, lab, b, dense = oracle.cubic_sweep(L, 1.0, T, q, 41, t, sp, dense=True)
+        counts = np.bincount(sp, minlength=q)
+        assert int(rec["m_sum"]) == counts.max(), (t, counts, int(rec["m_sum"]))
+        winners.add(int(counts.argmax()))
+    assert len(winners) == q, winners
+
+
 def cube2_states(q: int):
     """All q^8 configurations of the 2x2x2 torus and their e_sum over the 24
     edges (s, s + d), counted per direction: Ising sum of s_i s_j, Potts

@@ -64,6 +64,14 @@ MUTANTS = [
     ("cubic labels skip the +z bonds", "for (int d = 0; d < 3; ++d)\n            if (bonds[s] & (1u << d)) uf_union",
      "for (int d = 0; d < 2; ++d)\n            if (bonds[s] & (1u << d)) uf_union",
      [lambda: cubic.test_labels_are_min_site_components(4, 0.3), cubic.test_2x2x2_ising_exact_enumeration_chi2]),
+    ("Potts hot start not random", "        spins[s] = potts_value(r[0], (uint32_t)q);",
+     "        spins[s] = (int8_t)(s % (uint32_t)q);", [potts.test_hot_start_site_by_site_and_iid_uniform]),
+    ("Potts hot start from word 1", "        spins[s] = potts_value(r[0], (uint32_t)q);",
+     "        spins[s] = potts_value(r[1], (uint32_t)q);", [potts.test_hot_start_site_by_site_and_iid_uniform]),
+    ("cubic Potts m_sum skips the last value",
+     "for (int32_t k = 0; k < q; ++k)\n            if (count[k] > m) m = count[k];",
+     "for (int32_t k = 0; k < q - 1; ++k)\n            if (count[k] > m) m = count[k];",
+     [lambda: cubic.test_potts_m_sum_is_the_largest_population(3)]),
 ]
 
 

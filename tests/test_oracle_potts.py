@@ -38,6 +38,27 @@ def test_init_and_value_ranges():
     assert min(vals) >= 0 and max(vals) < q
 
 
+def test_hot_start_site_by_site_and_iid_uniform():
+    """Hot start (R14): site s takes floor(w q / 2^32) of word 0 of the
+    Philox output for counter {s, 0, 2, 0}, recomputed here with the
+    independent Python Philox that the known-answer vectors pin; on a larger
+    lattice single values and horizontal neighbour pairs are uniform (chi^2),
+    as i.i.d. uniform values must be."""
+    for q, L, seed in ((5, 12, 9), (3, 8, 2 ** 40 + 7), (8, 8, 123)):
+        key = exact.seed_key(seed)
+        want = np.array([(exact.philox4x32_10([s, 0, 2, 0], key)[0] * q) >> 32 for s in range(L * L)])
+        assert np.array_equal(oracle.potts_init(L, seed, q), want), (q, L, seed)
+    q, L = 5, 192
+    hot = oracle.potts_init(L, 31, q).astype(np.int64)
+    n = L * L
+    chi2, dof, p = exact.chi2_pvalue(np.bincount(hot, minlength=q), np.full(q, n / q))
+    assert p > 1e-4, (chi2, dof)
+    grid = hot.reshape(L, L)
+    pair = (grid * q + np.roll(grid, -1, axis=1)).ravel()
+    chi2, dof, p = exact.chi2_pvalue(np.bincount(pair, minlength=q * q), np.full(q * q, n / q ** 2))
+    assert p > 1e-4, (chi2, dof)
+
+
 def test_q2_is_ising_at_half_the_coupling():
     """q = 2 Potts at beta is the Ising model at beta / 2: with e_I = 2 e_P - 2N
     the final states of independent chains follow the exact 4x4 Ising law."""

@@ -42,6 +42,10 @@ ALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # multiplies + 4 xors) = 60 ops per call; a site needs 1/2 call for its two
 # bond words plus 1/TW of a call for the flip bits of its tile row.
 TILE_BYTES_PER_SITE = 2.0
+# Stream model of one sweep of a bond / label / flip pipeline, bytes per
+# site-update: bonds 2 (spin in, mask out), labels 5 (mask in, 32-bit label
+# out), flip 5 (label in, spin out).
+MODEL_BYTES_PER_SITE = 12.0
 PHILOX_OPS = 60.0
 # Paths with 32-bit labels in HBM, algorithmic bytes per site and sweep.
 # Label equivalence: bonds 2 (spins in, mask out), label init 4, every pass
@@ -83,21 +87,33 @@ def load_counters(L: int):
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2
 
 
-def cpu_baseline(L: int, seed: int):
-    import oracle
+def cpu_baseline(args):
+    """The sequential C oracle timed on bounded samples of the workloads, in a
+    child process that never touches the GPU (oracle/cpu_rate.py): the
+    headline lattice, L = 64 and L = 1024 on one core each, and the
+    256-replica grid over all usable host cores (at most 16)."""
+    import subprocess
 
-    T = oracle.threshold(BETA_C, 1.0)
-    spins = oracle.init(L, seed)
-    t0 = time.perf_counter()
-    oracle.run(L, 1.0, T, seed, 0, 1, spins)
-    dt = time.perf_counter() - t0
+    cmd = [sys.executable, "-m", "oracle.cpu_rate", "--l16384-sweeps", "1",
+           "--l1024-sweeps", str(args.cpu_l1024_sweeps), "--grid-sweeps", str(args.cpu_grid_sweeps)]
+    res = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=900)
+    if res.returncode != 0:
+        raise RuntimeError(f"oracle timing failed: {res.stderr[-2000:]}")
+    legs = json.loads(res.stdout.strip().splitlines()[-1])
+    head = legs["L16384"]
     return {
-        "value": L * L / dt,
+        "value": head["value"],
         "unit": "site-updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"one sweep of the L={L} beta_c lattice from a hot start (seed {seed}); "
-                  f"sequential C oracle, {dt:.1f} s",
+        "sample": f"one sweep of the L=16384 beta_c lattice from a hot start (seed 4), sequential C "
+                  f"oracle on one core, {head['seconds']:.1f} s; the 200-sweep rate is extrapolated from it",
+        "legs": {
+            "L64_beta_c_1000_sweeps_1_core": legs["L64"],
+            "L1024_three_betas_1_core": legs["L1024"],
+            "grid_256_replicas_all_cores": legs["grid"],
+        },
+        "usable_host_cores": legs["usable_cores"],
     }
 
 
@@ -129,6 +145,8 @@ def batched_vs_plain(args):
     b.close()
     print(f"[bench] batched: {bdt * 1e3:.2f} ms for {args.batch_steps} sweeps", file=sys.stderr, flush=True)
 
+    # plain: one sim per replica, each on its own stream, driven by one
+    # sw_sweep(n) per replica (n sweeps replayed from the sim's own graph)
     sims = [sw.Sim(int(L[r]), float(beta[r]), 1.0, int(seed[r])) for r in range(len(L))]
     for s_ in sims:
         s_.sweep(2)
@@ -136,17 +154,27 @@ def batched_vs_plain(args):
         s_.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for s_ in sims:
+        s_.sweep(args.batch_steps)
+    for s_ in sims:
+        s_.sync()
+    pdt = time.perf_counter() - t0
+    # the same sims driven one sweep at a time, replica after replica (as a
+    # caller that steps every replica in lockstep would)
+    t0 = time.perf_counter()
     for _ in range(args.plain_steps):
         for s_ in sims:
             s_.sweep(1)
     for s_ in sims:
         s_.sync()
-    pdt = time.perf_counter() - t0
+    idt = time.perf_counter() - t0
     for s_ in sims:
         s_.close()
-    print(f"[bench] plain: {pdt * 1e3:.2f} ms for {args.plain_steps} sweeps", file=sys.stderr, flush=True)
+    print(f"[bench] plain: {pdt * 1e3:.2f} ms for {args.batch_steps} sweeps per replica stream; "
+          f"{idt * 1e3:.2f} ms for {args.plain_steps} lockstep sweeps", file=sys.stderr, flush=True)
     bval = sites * args.batch_steps / bdt
-    pval = sites * args.plain_steps / pdt
+    pval = sites * args.batch_steps / pdt
+    ival = sites * args.plain_steps / idt
     return {
         "workload": "256 replicas, L = {64,128,256,512,1024}[r mod 5], beta_k = 0.40 + 0.08 k/31 "
                     "(k = r // 8), seed 1000 + r, hot start, J = 1",
@@ -154,9 +182,12 @@ def batched_vs_plain(args):
         "autotune_ms_per_sweep": {str(k): v for k, v in tune_ms.items()},
         "value": bval, "unit": "site-updates/s", "sweeps": args.batch_steps,
         "ms_per_step": bdt * 1e3 / args.batch_steps,
-        "plain_value": pval, "plain_sweeps": args.plain_steps,
-        "plain_ms_per_step": pdt * 1e3 / args.plain_steps,
+        "plain": {"how": "256 plain sims, each on its own stream, one sw_sweep(n) call per replica",
+                  "value": pval, "sweeps": args.batch_steps, "ms_per_step": pdt * 1e3 / args.batch_steps},
+        "plain_lockstep": {"how": "the same sims, one sw_sweep(1) per replica per sweep",
+                           "value": ival, "sweeps": args.plain_steps, "ms_per_step": idt * 1e3 / args.plain_steps},
         "batched_over_plain": bval / pval,
+        "batched_over_plain_lockstep": bval / ival,
     }
 
 
@@ -294,6 +325,41 @@ def serving(args):
     }
 
 
+def serving_saturated(args):
+    """Serving capacity: every job is queued at time 0 (the queue is never
+    empty while jobs remain), so the GPU is never waiting for arrivals; job
+    mix as in the Poisson leg (its own seed); latency = finish time."""
+    import numpy as np
+
+    import paper_2302_14720_amd as sw
+
+    rng = np.random.default_rng(4048)
+    n = args.serve_sat_jobs
+    L = (np.round(np.exp(rng.uniform(np.log(128), np.log(4096), n)) / 32).astype(int) * 32).clip(128, 4096)
+    beta = rng.uniform(0.35, 0.55, n)
+    sweeps = rng.integers(100, 10001, n)
+    work = int((L.astype(np.int64) ** 2 * sweeps).sum())
+    print(f"[bench] serving (saturated): {n} jobs, {work:.3e} site-updates", file=sys.stderr, flush=True)
+    srv = sw.Server(16 << 30, max_jobs=256)
+    t0 = time.perf_counter()
+    ids = {srv.submit(int(L[i]), float(beta[i]), 1.0, 9000 + i, int(sweeps[i])): i for i in range(n)}
+    finish = {}
+    while len(finish) < n:
+        for jid in srv.step(20):
+            finish[ids[jid]] = time.perf_counter() - t0
+            srv.release(jid)
+    span = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([finish[i] for i in range(n)])
+    return {
+        "workload": f"{n} jobs all queued at t = 0, L log-uniform in [128, 4096] (multiples of 32), "
+                    "beta U[0.35, 0.55], sweeps U[100, 10000], hot start, 16 GiB pool",
+        "jobs": n, "site_updates": work, "makespan_s": span,
+        "value": work / span, "unit": "site-updates/s",
+        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+    }
+
+
 def label_equivalence(args, tile_rate):
     """The paper's own cluster formation (iterated label equivalence in
     global memory, one cooperative kernel) against the tile pipeline: the
@@ -383,13 +449,19 @@ def main() -> int:
     ap.add_argument("--batch-steps", type=int, default=200,
                     help="timed sweeps of the 256-replica batch")
     ap.add_argument("--plain-steps", type=int, default=10,
-                    help="timed sweeps of the same replicas as plain sims, one sw_sweep per replica per sweep")
+                    help="timed lockstep sweeps of the same replicas as plain sims, one sw_sweep(1) per replica per sweep")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--serve-jobs", type=int, default=48, help="jobs of the serving leg (0 = skip)")
     ap.add_argument("--le-steps", type=int, default=10,
                     help="timed sweeps of the label-equivalence comparison, its Potts and its "
                          "simple cubic runs (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the serving leg, jobs/s")
+    ap.add_argument("--serve-sat-jobs", type=int, default=64,
+                    help="jobs of the saturated serving leg, all queued at once (0 = skip)")
+    ap.add_argument("--cpu-l1024-sweeps", type=int, default=20,
+                    help="oracle sweeps per temperature of the L = 1024 CPU-baseline leg")
+    ap.add_argument("--cpu-grid-sweeps", type=int, default=10,
+                    help="oracle sweeps per replica of the all-cores grid CPU-baseline leg")
     ap.add_argument("--potts-steps", type=int, default=50,
                     help="timed sweeps of the q = 3 Potts model on the tile path (0 = skip)")
     ap.add_argument("--cubic-steps", type=int, default=20,
@@ -467,39 +539,43 @@ def main() -> int:
     per_sweep = {k: v for k, v in prof.items() if k != "resolve"}
     dom = max(per_sweep, key=per_sweep.get)
     t_dom = per_sweep[dom] * 1e-3
-    philox_per_site = 0.5 + 1.0 / tw
-    alu_ops = philox_per_site * PHILOX_OPS * N
-    tile_bytes = TILE_BYTES_PER_SITE * N
-    if dom == "tile":
-        hbm_ach = tile_bytes / t_dom / 1e9
-        alu_ach = alu_ops / t_dom / 1e12
-        hbm_frac = hbm_ach / HBM_PEAK_GBS
-        alu_frac = alu_ach / ALU_PEAK_TOPS
-        cnt = load_counters(L)
-        traffic = cnt.get("hbm_bytes_per_launch") if cnt else None
-        valu = cnt.get("valu_wave_instructions_per_launch") if cnt else None
-        if alu_frac >= hbm_frac:
-            roofline = {"bound": "alu", "achieved": alu_ach, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
-                        "frac": alu_frac, "traffic": traffic}
-        else:
-            roofline = {"bound": "hbm", "achieved": hbm_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": hbm_frac, "traffic": traffic}
-        roofline.update({"kernel": "k_tile", "kernel_ms": per_sweep[dom],
-                         "hbm_achieved_GBs": hbm_ach, "hbm_frac": hbm_frac,
-                         "alu_achieved_Tops": alu_ach, "alu_frac": alu_frac,
-                         # issued VALU wave instructions (all work, not only the
-                         # algorithmic Philox ops) against the issue ceiling
-                         "valu_issue_frac": (valu / t_dom / VALU_ISSUE_PEAK) if valu else None})
-    else:
-        roofline = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
-                    "traffic": None, "kernel": dom, "kernel_ms": per_sweep[dom]}
+    # Roofline against the stream model of a bond / label / flip sweep
+    # (12 B per site-update: bonds read a spin and write a mask, labelling
+    # reads the mask and writes a 32-bit label, the flip reads the label and
+    # writes a spin), credited to the dominant kernel, which does all three
+    # for N sites per launch; and the same model over the whole timed sweep.
+    model_bytes = MODEL_BYTES_PER_SITE * N
+    ach = model_bytes / t_dom / 1e9
+    cnt = load_counters(L)
+    traffic = cnt.get("hbm_bytes_per_launch") if (cnt and dom == "tile") else None
+    valu = cnt.get("valu_wave_instructions_per_launch") if (cnt and dom == "tile") else None
+    alu_ach = (0.5 + 1.0 / tw) * PHILOX_OPS * N / t_dom / 1e12
+    design_ach = TILE_BYTES_PER_SITE * N / t_dom / 1e9
+    roofline = {
+        "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "kernel": "k_tile" if dom == "tile" else dom, "kernel_ms": per_sweep[dom],
+        "algorithmic_bytes_per_launch": model_bytes,
+        "model": "12 B per site-update (bond 1R+1W, label 1R+4W, flip 4R+1W) x N sites per launch",
+        "traffic_bytes_per_site": (traffic / N) if traffic else None,
+        "whole_sweep": {"ms": dt * 1e3 / args.steps, "achieved_GBs": value * MODEL_BYTES_PER_SITE / 1e9,
+                        "frac": value * MODEL_BYTES_PER_SITE / 1e9 / HBM_PEAK_GBS},
+        "diagnostics": {
+            # the bytes this design actually has to move in k_tile (one spin
+            # byte in, one out), the Philox integer work, and the issued VALU
+            # instructions against the issue ceiling
+            "design_bytes_per_site": TILE_BYTES_PER_SITE, "design_GBs": design_ach,
+            "design_hbm_frac": design_ach / HBM_PEAK_GBS,
+            "philox_alu_Tops": alu_ach, "philox_alu_frac": alu_ach / ALU_PEAK_TOPS,
+            "valu_issue_frac": (valu / t_dom / VALU_ISSUE_PEAK) if valu else None,
+        },
+    }
     # measured HBM bytes of every kernel of a sweep (committed counters of the
     # current kernel source), against the 12 B/site stream model
-    cnt_all = load_counters(L)
     sweep_hbm = None
-    if cnt_all and cnt_all.get("sweep_hbm_bytes_per_site"):
-        bps = cnt_all["sweep_hbm_bytes_per_site"]
-        sweep_hbm = {"measured_bytes_per_site": bps, "model_bytes_per_site": 12.0,
+    if cnt and cnt.get("sweep_hbm_bytes_per_site"):
+        bps = cnt["sweep_hbm_bytes_per_site"]
+        sweep_hbm = {"measured_bytes_per_site": bps, "model_bytes_per_site": MODEL_BYTES_PER_SITE,
                      "GBs": value * bps / 1e9, "frac": value * bps / 1e9 / HBM_PEAK_GBS}
 
     out = {
@@ -520,8 +596,6 @@ def main() -> int:
                         f"hot start seed {args.seed}, int8 spins, Philox4x32-10",
             "L": L, "beta": BETA_C, "J": 1.0, "tile": tw, "start": "hot",
         },
-        # site-updates/s x 12 B (the classic bond/label/flip stream model) / 8 TB/s
-        "effective_roofline_12B_frac": value * 12.0 / (HBM_PEAK_GBS * 1e9),
         "sweep_hbm": sweep_hbm,
         "roofline": roofline,
         "kernel_ms": prof,
@@ -530,14 +604,16 @@ def main() -> int:
                        "first_sweep_max_cluster": int(crec["max_cluster"])},
         "batched": None if args.no_batched else batched_vs_plain(args),
         "serving": serving(args) if args.serve_jobs > 0 else None,
+        "serving_saturated": serving_saturated(args) if args.serve_sat_jobs > 0 else None,
         "potts_tile": potts_tile(args) if args.potts_steps > 0 else None,
         "cubic": cubic(args) if args.cubic_steps > 0 else None,
         "paper_table": paper_table(args) if args.paper_sweeps > 0 else None,
         "label_equivalence": label_equivalence(args, value) if args.le_steps > 0 else None,
     }
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on one L=%d sweep" % L, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(L, args.seed)
+        print("[bench] timing the CPU oracle (one L=16384 sweep, L=64, L=1024, the replica grid)",
+              file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out))
     return 0
 

@@ -107,8 +107,13 @@ int sw_config_init(sw_config *cfg, int32_t L, double beta, double J, uint64_t se
 size_t sw_workspace_bytes(int32_t L);
 size_t sw_workspace_bytes_ex(const sw_config *cfg);
 
-/* Creates a sim (hot start, t = 0) that allocates its own device memory and
- * its own stream (default priority).  *out receives the handle. */
+/* Creates a sim of the L x L periodic lattice with coupling J at inverse
+ * temperature beta, in the random initial configuration of Sec. 2 (Fig. 1:
+ * i.i.d. spins, up or down with probability 1/2, drawn from `seed`), t = 0.
+ * The bond probability of Sec. 2.1 is fixed here, once, as the threshold T.
+ * The sim allocates its own device memory and its own stream (default
+ * priority).  *out receives the handle; SW_EINVAL for L, beta or J outside
+ * their domain (see sw_config), SW_ENOMEM / SW_EHIP if the device refuses. */
 int sw_create(int32_t L, double beta, double J, uint64_t seed, sw_sim **out);
 
 /* As sw_create, but carves every device buffer out of the caller's
@@ -151,27 +156,39 @@ int sw_sync(sw_sim *sim);
  * stream).  SW_ESTATE if no sweep has run since create / reset / set_spins. */
 int sw_observables(sw_sim *sim, sw_obs *out);
 
-/* Copies records of sweeps first .. first+count-1 into out[0..count-1]
- * (waits).  SW_ERANGE unless all of them ran since the last create / reset /
- * set_spins and are still held in the ring. */
+/* Per-sweep series of the measurements of Sec. 2.5 (magnetisation and
+ * energy of every new configuration, with the statistics of the clusters of
+ * Sec. 2.3 that produced it): copies records of sweeps first ..
+ * first+count-1 into out[0..count-1] (host memory, caller-owned; waits).
+ * SW_ERANGE unless all of them ran since the last create / reset /
+ * set_spins and are still held in the ring; SW_EINVAL for a NULL out. */
 int sw_series(sw_sim *sim, int64_t first, int64_t count, sw_obs *out);
 
-/* Exact cluster-size histogram of the last sweep: counts[s] = number of
- * clusters of size s, s = 0..N (len >= N+1).  Needs SW_FLAG_DENSE_HIST. */
+/* Exact cluster-size histogram of the last sweep's clusters (the connected
+ * components of Sec. 2.3): counts[s] = number of clusters of size s,
+ * s = 0..N, into host memory of len >= N+1 words.  Needs
+ * SW_FLAG_DENSE_HIST (SW_ESTATE otherwise, or before the first sweep);
+ * SW_ERANGE if len is too small. */
 int sw_cluster_hist(sw_sim *sim, uint64_t *counts, int64_t len);
 
 /* Current spins (int8 +-1, site order s = y*L + x) to host memory;
  * n must equal N = L*L. */
 int sw_get_spins(sw_sim *sim, int8_t *host, int64_t n);
 
-/* Replaces the spins (each +1 or -1, n == N) and makes next_sweep the index
- * of the next sweep -- for checkpoint / resume and one-step parity checks.
- * Records before next_sweep become unavailable. */
+/* Replaces the spins (host int8, each +1 or -1, n == N, site order
+ * s = y*L + x) and makes next_sweep the index of the next sweep.  A sweep
+ * (Sec. 2) depends only on the current configuration and on randomness
+ * keyed by (seed, sweep, site), so this resumes a chain from a checkpoint
+ * and lets one sweep be compared against a reference.  Records before
+ * next_sweep become unavailable.  SW_EINVAL for a value other than +-1
+ * (Potts: outside 0..q-1), SW_ERANGE for a wrong n. */
 int sw_set_spins(sw_sim *sim, const int8_t *host, int64_t n, uint64_t next_sweep);
 
-/* Canonical labels (smallest site of the cluster) of the last sweep's
- * clusters to host memory, n == N.  Needs SW_FLAG_LABELS and a completed
- * sweep. */
+/* Labels of the last sweep's clusters (Sec. 2.3: every site ends with the
+ * lowest label of its cluster, labels starting as site indices, i.e. the
+ * smallest site index of the cluster) to host memory (uint32, n == N, site
+ * order).  Needs SW_FLAG_LABELS and a completed sweep (SW_ESTATE
+ * otherwise); SW_ERANGE for a wrong n. */
 int sw_get_labels(sw_sim *sim, uint32_t *host, int64_t n);
 
 /* Sims created with SW_FLAG_LABEL_EQUIV form clusters as the paper does
@@ -244,7 +261,7 @@ const char *sw_last_error(void);
  * seed[r] and its own records; its spins, clusters and records are bit for
  * bit those of a plain sim created with the same parameters and swept the
  * same number of times.  All replicas share the sweep counter t.
- * Limits: 1 <= n <= 4096; every L[r] as for sw_create (the tile is 64 when
+ * Limits: 1 <= n <= 4095; every L[r] as for sw_create (the tile is 64 when
  * every L[r] is a multiple of 64, else 32); no labels or dense histogram. */
 typedef struct sw_batch sw_batch;
 
@@ -342,7 +359,7 @@ size_t sw_server_job_bytes_potts(int32_t L, int32_t q, int64_t sweeps);
 
 /* Creates a server with a device memory pool of pool_bytes: `pool` is a
  * 256-byte-aligned device buffer the caller keeps alive until
- * sw_server_destroy, or NULL (the library allocates it).  max_jobs (1..4096)
+ * sw_server_destroy, or NULL (the library allocates it).  max_jobs (1..4095)
  * bounds the active jobs.  hip_stream: the stream for all work, or NULL
  * (the library creates one). */
 int sw_server_create(void *pool, size_t pool_bytes, int32_t max_jobs, void *hip_stream, sw_server **out);
@@ -368,7 +385,11 @@ int sw_server_step(sw_server *server, int64_t n, int64_t *done_ids, int32_t cap,
 /* State and progress of a job (SW_ERANGE for an unknown id). */
 int sw_server_job_info(sw_server *server, int64_t job_id, sw_job_info *info);
 
-/* Records first .. first+count-1 of an admitted job (sweeps run so far). */
+/* Records first .. first+count-1 of an admitted job (Sec. 2.5 measurements,
+ * as sw_series).  A finished job has records 0 .. sweeps_total-1.  An active
+ * job that has run `done` sweeps has records 0 .. done-2: the energy and
+ * magnetisation of record done-1 are measured by the job's next sweep, so
+ * asking for it gives SW_ERANGE until then. */
 int sw_server_job_series(sw_server *server, int64_t job_id, int64_t first, int64_t count, sw_obs *out);
 
 /* Final spins of a finished job (n == L*L); SW_ESTATE before it is done. */

@@ -98,7 +98,9 @@ hipError_t launch_resolve(const Dev &d, hipStream_t s);
 constexpr uint32_t kMapShift = 20;
 constexpr uint32_t kMapMask = (1u << kMapShift) - 1u;
 constexpr uint32_t kMapNone = 0xFFFFFFFFu;
-constexpr int32_t kMaxReplicas = 4096;
+// 4095 so that no entry (replica <= 4094) can equal kMapNone, whatever the unit
+constexpr int32_t kMaxReplicas = 4095;
+static_assert(((uint32_t)(kMaxReplicas - 1) << kMapShift | kMapMask) != kMapNone, "map entry collides with kMapNone");
 
 struct BatchDev {
     const Dev *devs;       // [n] the replicas' Dev, in device memory

@@ -416,7 +416,16 @@ int sw_server_job_series(sw_server *s, int64_t id, int64_t first, int64_t count,
     if (rc != SW_OK) return rc;
     if (j->state == SW_JOB_QUEUED) return fail(SW_ESTATE, "job has not started");
     if (count < 0 || (count > 0 && !out)) return fail(SW_EINVAL, "bad count or NULL out");
-    if (first < 0 || first + count > j->done) return fail(SW_ERANGE, "records requested outside the sweeps run");
+    // The energy and magnetisation of an active job's last record are those
+    // of the configuration its last sweep left, measured by the job's next
+    // sweep (or by the closing pass when it finishes): until then that
+    // record is incomplete and is not handed out.
+    const int64_t avail = j->state == SW_JOB_ACTIVE ? j->done - 1 : j->done;
+    if (first < 0 || first + count > avail)
+        return fail(SW_ERANGE, j->state == SW_JOB_ACTIVE
+                                   ? "records requested outside the sweeps run (an active job's last record is "
+                                     "complete only after its next sweep)"
+                                   : "records requested outside the sweeps run");
     if (count == 0) return SW_OK;
     rc = srv_device(s);
     if (rc != SW_OK) return rc;

@@ -56,40 +56,41 @@ def test_L1024_2000_sweeps(beta, seed):
     assert np.array_equal(final, state)
 
 
+@pytest.mark.parametrize("t", [0, 1, 2, 50, 199])
 @pytest.mark.parametrize("cold", [False, True])
-def test_L16384_benchmark_chain(cold):
+def test_L16384_one_step(cold, t):
     """The benchmark's lattice and launch configuration (torch workspace and
-    stream, graph-replayed sweeps): 200 sweeps, then the last one against
-    one oracle sweep from the GPU's own state; a cold start also checks its
-    first sweep (one near-spanning cluster) against the oracle."""
-    L, seed, n = 16384, 3 if cold else 4, 200
+    stream, graph-replayed sweeps), hot and cold start: the GPU chain runs to
+    sweep t, and sweep t is compared with one oracle sweep from the GPU's own
+    state -- record, spins and, for the first cold sweep (one near-spanning
+    cluster) and hot sweep 50, every site's canonical label.  The run to
+    sweep 199 also checks the invariants of all 200 records."""
+    L, seed = 16384, 3 if cold else 4
     N = L * L
     T = oracle.threshold(BETA_C, 1.0)
-    print(f"\n[case] L=16384 {'cold' if cold else 'hot'} start seed={seed}: {n} sweeps", flush=True)
-    with sw.Sim(L, BETA_C, 1.0, seed, init=sw.SW_INIT_COLD if cold else sw.SW_INIT_HOT) as s:
+    with_labels = (cold and t == 0) or (not cold and t == 50)
+    print(f"\n[case] L=16384 {'cold' if cold else 'hot'} start seed={seed}: sweep {t}"
+          f"{' with labels' if with_labels else ''}", flush=True)
+    flags = sw.SW_FLAG_LABELS if with_labels else 0
+    with sw.Sim(L, BETA_C, 1.0, seed, init=sw.SW_INIT_COLD if cold else sw.SW_INIT_HOT, flags=flags) as s:
         assert s.threshold == T
-        if cold:
-            s.sweep(1)
-            first = s.spins()
-            rec0 = s.series(0, 1)[0]
-            s.sweep(19)
-        else:
-            s.sweep(20)
-        s.sweep(n - 21)
+        s.sweep(t)
         state = s.spins()
         s.sweep(1)
-        recs = s.series(0, n)
+        recs = s.series(0, t + 1)
         final = s.spins()
-    _invariants(recs, N, "L=16384")
-    last, _, _ = oracle.sweep(L, 1.0, T, seed, n - 1, state)
-    assert last.tobytes() == recs[n - 1].tobytes()
+        lab = s.labels() if with_labels else None
+    if t == 0:
+        assert np.array_equal(state, oracle.init(L, seed, cold=cold))
+    if t == 199:
+        _invariants(recs, N, "L=16384")
+    rec, olab, _ = oracle.sweep(L, 1.0, T, seed, t, state)
+    assert rec.tobytes() == recs[t].tobytes()
     assert np.array_equal(final, state)
     del state, final
-    if cold:
-        sp = oracle.init(L, seed, cold=True)
-        r0, _, _ = oracle.sweep(L, 1.0, T, seed, 0, sp)
-        assert r0.tobytes() == rec0.tobytes()
-        assert np.array_equal(first, sp)
+    if with_labels:
+        bad = np.nonzero(lab != olab)[0]
+        assert bad.size == 0, f"labels differ at {bad.size} sites, first {bad[0]}"
 
 
 def test_grid_batch_5000_sweeps():

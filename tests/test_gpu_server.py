@@ -126,6 +126,10 @@ def test_server_errors():
         with pytest.raises(sw.SwError) as e:
             srv.series(j, 0, 4)
         assert e.value.code == sw.SW_ERANGE
+        with pytest.raises(sw.SwError) as e:  # the active job's last record is not complete yet
+            srv.series(j, 2, 1)
+        assert e.value.code == sw.SW_ERANGE
+        assert len(srv.series(j, 0, 2)) == 2
         for bad_q in (1, 9, -3):  # Potts q outside [2, 8]
             with pytest.raises(sw.SwError) as e:
                 srv.submit(64, 1.0, 1.0, 1, 10, q=bad_q)
@@ -183,3 +187,69 @@ def test_ising_and_potts_jobs_share_the_server():
             orec = oracle.potts_run(L, 1.0, oracle.potts_threshold(b, 1.0), q, s, 0, n, osp)
             _same_records(got, orec, f"job L={L} q={q} vs oracle")
             assert np.array_equal(spins, osp)
+
+
+def test_active_job_series_mid_run():
+    """Records of a job that is still running: 0 .. done-2 are complete and
+    equal the solo run's; record done-1 is refused until the next sweep."""
+    print("\n[case] server series of an active job", flush=True)
+    L, beta, seed, n = 128, BETA_C, 61, 30
+    ref, sp = _solo(L, beta, seed, n)
+    with sw.Server(1 << 26, max_jobs=4) as srv:
+        j = srv.submit(L, beta, 1.0, seed, n)
+        done = 0
+        for k in (1, 6, 9):
+            srv.step(k)
+            done += k
+            assert srv.info(j)["sweeps_done"] == done
+            with pytest.raises(sw.SwError) as e:
+                srv.series(j, 0, done)
+            assert e.value.code == sw.SW_ERANGE
+            if done >= 2:
+                _same_records(srv.series(j, 0, done - 1), ref[: done - 1], f"active job after {done} sweeps")
+        _drain(srv, 8)
+        assert srv.info(j)["state"] == sw.SW_JOB_DONE
+        _same_records(srv.series(j, 0, n), ref, "finished job")
+        assert np.array_equal(srv.spins(j), sp)
+
+
+def test_serving_workload_shaped_jobs_match_solo_runs():
+    """Jobs shaped like the serving workload: L log-uniform in [128, 4096]
+    rounded to a multiple of 32 (one of them 4096), beta uniform in
+    [0.35, 0.55], hot starts, a few hundred sweeps each; half are queued at
+    the start and half arrive while the first ones run, into a pool that
+    holds only some of them at once.  Every job's records and final spins
+    equal a plain sim run alone."""
+    rng = np.random.default_rng(2024)
+    njobs = 10
+    Ls = [int(round(math.exp(rng.uniform(math.log(128), math.log(4096))) / 32.0)) * 32 for _ in range(njobs)]
+    Ls[3] = 4096
+    betas = rng.uniform(0.35, 0.55, njobs)
+    sweeps = rng.integers(100, 401, njobs)
+    seeds = 7000 + np.arange(njobs)
+    need = [sw.Server.job_bytes(L, int(n)) for L, n in zip(Ls, sweeps)]
+    pool = max(need) + sum(sorted(need)[:3]) + 4096
+    print(f"\n[case] serving-shaped jobs L={Ls} sweeps={sweeps.tolist()} pool={pool}", flush=True)
+    results = {}
+    with sw.Server(pool, max_jobs=6) as srv:
+
+        def collect(jid):
+            info = srv.info(jid)
+            results[jid] = (srv.series(jid, 0, info["sweeps_done"]), srv.spins(jid))
+            srv.release(jid)
+
+        ids = {}
+        for i in range(njobs // 2):
+            ids[i] = srv.submit(Ls[i], float(betas[i]), 1.0, int(seeds[i]), int(sweeps[i]))
+        for _ in range(6):  # the first jobs run; the rest arrive mid-run
+            for jid in srv.step(37):
+                collect(jid)
+        for i in range(njobs // 2, njobs):
+            ids[i] = srv.submit(Ls[i], float(betas[i]), 1.0, int(seeds[i]), int(sweeps[i]))
+        _drain(srv, 37, collect=collect)
+        assert srv.status()["bytes_used"] == 0
+    for i in range(njobs):
+        got, spins = results[ids[i]]
+        ref, sp = _solo(Ls[i], float(betas[i]), int(seeds[i]), int(sweeps[i]))
+        _same_records(got, ref, f"job {i} L={Ls[i]} sweeps={int(sweeps[i])}")
+        assert np.array_equal(spins, sp), f"job {i} spins"

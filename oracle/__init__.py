@@ -102,6 +102,26 @@ def _bind(l: ctypes.CDLL) -> ctypes.CDLL:
     l.orc_cubic_run.restype = ctypes.c_int
     l.orc_cubic_chains.argtypes = [i32, f64, u32, i32, u64, i64, i32, P, P]
     l.orc_cubic_chains.restype = ctypes.c_int
+    l.orc_phi4_direction.argtypes = [u64, u32, P, P]
+    l.orc_phi4_direction.restype = None
+    l.orc_phi4_expm.argtypes = [f64]
+    l.orc_phi4_expm.restype = f64
+    l.orc_phi4_init.argtypes = [i32, i32, u64, i32, P]
+    l.orc_phi4_init.restype = None
+    l.orc_phi4_bonds.argtypes = [i32, i32, f64, u64, u32, P, P]
+    l.orc_phi4_bonds.restype = None
+    l.orc_phi4_label.argtypes = [i32, i32, P, P]
+    l.orc_phi4_label.restype = None
+    l.orc_phi4_flip.argtypes = [u64, u32, u32]
+    l.orc_phi4_flip.restype = i32
+    l.orc_phi4_reflect.argtypes = [i32, i32, u64, u32, P, P]
+    l.orc_phi4_reflect.restype = None
+    l.orc_phi4_observe.argtypes = [i32, i32, f64, u64, P, P, P]
+    l.orc_phi4_observe.restype = None
+    l.orc_phi4_sweep.argtypes = [i32, i32, f64, u64, u32, P, P, P, P]
+    l.orc_phi4_sweep.restype = ctypes.c_int
+    l.orc_phi4_run.argtypes = [i32, i32, f64, u64, u32, i64, P, P]
+    l.orc_phi4_run.restype = ctypes.c_int
     return l
 
 
@@ -358,3 +378,95 @@ def cubic_chains(L: int, J: float, T: int, q: int, seed0: int, nchains: int, nsw
     if lib().orc_cubic_chains(L, J, T, q, seed0, nchains, nsweeps, _p(e), _p(m)) != 0:
         raise MemoryError("oracle cubic chains: allocation failed")
     return e, m
+
+
+# ------------------------------------------------- O(4) model (phi^4, unit fields)
+# D-dimensional periodic hypercube of side L, s = sum_mu x_mu L^mu, fields as
+# an (N, 4) float64 array; one multicluster Wolff-embedding update per sweep.
+PHI4_OBS_DTYPE = np.dtype(
+    [
+        ("sweep", "<u8"),
+        ("e_fix", "<i8"),
+        ("action", "<f8"),
+        ("m_fix", "<i8", (4,)),
+        ("m_abs", "<f8"),
+        ("n_clusters", "<u8"),
+        ("max_cluster", "<u8"),
+        ("sum_sq_sizes", "<u8"),
+        ("hist_log2", "<u8", (33,)),
+    ]
+)
+
+
+def phi4_direction(seed: int, t: int):
+    """(r, rr): the unnormalised random direction of sweep t and r . r."""
+    r = np.zeros(4, dtype=np.float64)
+    rr = np.zeros(1, dtype=np.float64)
+    lib().orc_phi4_direction(seed, t, _p(r), _p(rr))
+    return r, float(rr[0])
+
+
+def phi4_expm(a: float) -> float:
+    return float(lib().orc_phi4_expm(a))
+
+
+def phi4_init(D: int, L: int, seed: int, cold: bool = False) -> np.ndarray:
+    f = np.empty((L ** D, 4), dtype=np.float64)
+    lib().orc_phi4_init(D, L, seed, 1 if cold else 0, _p(f))
+    return f
+
+
+def _phi(phi: np.ndarray, n: int) -> np.ndarray:
+    assert phi.dtype == np.float64 and phi.flags.c_contiguous and phi.shape == (n, 4)
+    return phi
+
+
+def phi4_bonds(D: int, L: int, kappa: float, seed: int, t: int, phi: np.ndarray) -> np.ndarray:
+    f = _phi(phi, L ** D)
+    b = np.empty(L ** D, dtype=np.uint8)
+    lib().orc_phi4_bonds(D, L, kappa, seed, t, _p(f), _p(b))
+    return b
+
+
+def phi4_label(D: int, L: int, bond_mask: np.ndarray) -> np.ndarray:
+    b = np.ascontiguousarray(bond_mask, dtype=np.uint8)
+    assert b.size == L ** D
+    lab = np.empty(L ** D, dtype=np.uint32)
+    lib().orc_phi4_label(D, L, _p(b), _p(lab))
+    return lab
+
+
+def phi4_flip(seed: int, t: int, root: int) -> int:
+    return int(lib().orc_phi4_flip(seed, t, root))
+
+
+def phi4_reflect(D: int, L: int, seed: int, t: int, labels: np.ndarray, phi: np.ndarray) -> None:
+    """Reflects, in place, the sites of the clusters drawn for reflection."""
+    lab = np.ascontiguousarray(labels, dtype=np.uint32)
+    lib().orc_phi4_reflect(D, L, seed, t, _p(lab), _p(_phi(phi, L ** D)))
+
+
+def phi4_observe(D: int, L: int, kappa: float, sweep: int, phi: np.ndarray, labels=None):
+    lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.uint32)
+    rec = np.zeros(1, dtype=PHI4_OBS_DTYPE)
+    lib().orc_phi4_observe(D, L, kappa, sweep, _p(_phi(phi, L ** D)), _p(lab), _p(rec))
+    return rec[0]
+
+
+def phi4_sweep(D: int, L: int, kappa: float, seed: int, t: int, phi: np.ndarray):
+    """One multicluster update in place on ``phi``; returns (record, labels, bonds)."""
+    n = L ** D
+    lab = np.empty(n, dtype=np.uint32)
+    b = np.empty(n, dtype=np.uint8)
+    rec = np.zeros(1, dtype=PHI4_OBS_DTYPE)
+    if lib().orc_phi4_sweep(D, L, kappa, seed, t, _p(_phi(phi, n)), _p(lab), _p(b), _p(rec)) != 0:
+        raise MemoryError("oracle phi4 sweep: allocation failed")
+    return rec[0], lab, b
+
+
+def phi4_run(D: int, L: int, kappa: float, seed: int, t0: int, count: int, phi: np.ndarray) -> np.ndarray:
+    """``count`` updates in place on ``phi``; returns their records."""
+    recs = np.zeros(count, dtype=PHI4_OBS_DTYPE)
+    if lib().orc_phi4_run(D, L, kappa, seed, t0, count, _p(_phi(phi, L ** D)), _p(recs)) != 0:
+        raise MemoryError("oracle phi4 run: allocation failed")
+    return recs

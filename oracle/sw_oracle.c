@@ -627,3 +627,264 @@ int orc_cubic_chains(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed0,
     free(sp);
     return 0;
 }
+
+/* ================================================================== */
+/* O(4) phi^4 theory: the paper's second workload (Sec. 3), one        */
+/* multicluster update of the Wolff embedding (Wolff's algorithm for   */
+/* continuous spins, with every cluster reflected independently, as in */
+/* Swendsen-Wang).  The paper fixes the bond probability (eq. 2) and   */
+/* the reflection (eq. 3) but gives neither the self-coupling lambda   */
+/* nor the radial update; the reading used is lambda -> infinity:      */
+/* every field phi_x is a unit 4-vector and the weight of a            */
+/* configuration is exp(2 kappa sum_<xy> phi_x . phi_y), which the     */
+/* cluster update samples on its own.                                  */
+/*                                                                     */
+/* The lattice is a D-dimensional periodic hypercube of side L         */
+/* (D = 4 in the paper; any D here, so that D = 1 can be checked       */
+/* against the exact ring), site s = sum_mu x_mu L^mu, x_0 fastest;     */
+/* each site owns the D links to s + mu.  Fields are 4 doubles per     */
+/* site.  All floating point is IEEE-754 double, evaluated operation   */
+/* by operation in the order written (this file is built as ISO C, so  */
+/* no multiply-add is contracted):                                     */
+/*   uniform of a word w     v = (w + 0.5) 2^-31 - 1, in (-1, 1)       */
+/*   random direction of     attempt k = 0..63: Philox({k, t, 5, 0})    */
+/*   sweep t                 gives v_0..v_3; accepted iff               */
+/*                           rr = ((v0 v0 + v1 v1) + v2 v2) + v3 v3 < 1; */
+/*                           r = v, unnormalised (n = r / |r|); after   */
+/*                           64 rejections r = (1, 0, 0, 0)             */
+/*   projection              p_x = ((f0 r0 + f1 r1) + f2 r2) + f3 r3    */
+/*   link (x, mu) bonded iff a = ((p_x p_y) (4 kappa)) / rr > 0 and     */
+/*                           u < 1 - E(a), u = w 2^-32, w = word mu of  */
+/*                           Philox({x, t, 7, 0}), y = x + mu            */
+/*   E(a) ~ exp(-a)          halve b = a while b > 1/8 (k times), then  */
+/*                           q = 1; q = 1 - (q b) c_j for j = 13..1     */
+/*                           (c_j = 1 / j rounded), then square q k     */
+/*                           times (relative error below 1e-14)         */
+/*   cluster reflected iff   bit root mod 128 of Philox({root >> 7, t,  */
+/*                           6, 0}) is 1 (root = smallest site)         */
+/*   reflection (eq. 3)      f = (2 p_x) / rr; phi^a -= f r^a            */
+/*   hot start               site x, attempt k = 0..63: Philox({x, k,   */
+/*                           8, 0}), v and vv as above, accepted iff    */
+/*                           vv < 1: phi^a = v^a / sqrt(vv); after 64   */
+/*                           rejections (1, 0, 0, 0); cold start        */
+/*                           (1, 0, 0, 0) everywhere                    */
+/*   measurement             e_fix = sum over links of                  */
+/*                           rint(2^32 phi_x . phi_y), m_fix[a] = sum   */
+/*                           of rint(2^32 phi_x^a), exact int64 sums    */
+/* ================================================================== */
+static uint32_t phi4_sites(int32_t D, int32_t L)
+{
+    uint32_t n = 1u;
+    for (int32_t d = 0; d < D; ++d) n *= (uint32_t)L;
+    return n;
+}
+
+/* s + mu-hat on the periodic D-dimensional lattice of side L */
+static uint32_t phi4_step(uint32_t s, uint32_t L, int32_t mu)
+{
+    uint32_t stride = 1u;
+    for (int32_t d = 0; d < mu; ++d) stride *= L;
+    uint32_t x = (s / stride) % L;
+    return x + 1u == L ? s - x * stride : s + stride;
+}
+
+static double phi4_uniform(uint32_t w)
+{
+    return ((double)w + 0.5) * 0x1p-31 - 1.0;
+}
+
+static double phi4_dot(const double a[4], const double b[4])
+{
+    return ((a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]) + a[3] * b[3];
+}
+
+/* random direction of sweep t: r (unnormalised) and rr = r . r */
+void orc_phi4_direction(uint64_t seed, uint32_t t, double r[4], double *rr)
+{
+    for (uint32_t k = 0; k < 64u; ++k) {
+        uint32_t w[4];
+        philox_seed(seed, k, t, 5u, w);
+        double v[4];
+        for (int a = 0; a < 4; ++a) v[a] = phi4_uniform(w[a]);
+        double vv = phi4_dot(v, v);
+        if (vv < 1.0) {
+            for (int a = 0; a < 4; ++a) r[a] = v[a];
+            *rr = vv;
+            return;
+        }
+    }
+    r[0] = 1.0; r[1] = r[2] = r[3] = 0.0;
+    *rr = 1.0;
+}
+
+/* E(a), the evaluation of exp(-a) (a > 0) used by the bond test */
+double orc_phi4_expm(double a)
+{
+    double b = a;
+    int k = 0;
+    while (b > 0.125) {
+        b = b * 0.5;
+        ++k;
+    }
+    double q = 1.0;
+    for (int j = 13; j >= 1; --j) {
+        double c = 1.0 / (double)j;
+        q = 1.0 - (q * b) * c;
+    }
+    for (int i = 0; i < k; ++i) q = q * q;
+    return q;
+}
+
+void orc_phi4_init(int32_t D, int32_t L, uint64_t seed, int32_t cold, double *phi)
+{
+    uint32_t n = phi4_sites(D, L);
+    for (uint32_t s = 0; s < n; ++s) {
+        double *f = phi + 4u * (size_t)s;
+        f[0] = 1.0; f[1] = f[2] = f[3] = 0.0;
+        if (cold) continue;
+        for (uint32_t k = 0; k < 64u; ++k) {
+            uint32_t w[4];
+            philox_seed(seed, s, k, 8u, w);
+            double v[4];
+            for (int a = 0; a < 4; ++a) v[a] = phi4_uniform(w[a]);
+            double vv = phi4_dot(v, v);
+            if (vv < 1.0) {
+                double len = sqrt(vv);
+                for (int a = 0; a < 4; ++a) f[a] = v[a] / len;
+                break;
+            }
+        }
+    }
+}
+
+/* Bonds of sweep t (eq. 2): bonds[s] bit mu = link (s, s + mu) bonded. */
+void orc_phi4_bonds(int32_t D, int32_t L, double kappa, uint64_t seed, uint32_t t,
+                    const double *phi, uint8_t *bonds)
+{
+    uint32_t n = phi4_sites(D, L);
+    double r[4], rr;
+    orc_phi4_direction(seed, t, r, &rr);
+    double k4 = 4.0 * kappa;
+    for (uint32_t s = 0; s < n; ++s) {
+        uint32_t w[4];
+        philox_seed(seed, s, t, 7u, w);
+        double px = phi4_dot(phi + 4u * (size_t)s, r);
+        uint8_t b = 0;
+        for (int32_t mu = 0; mu < D; ++mu) {
+            uint32_t y = phi4_step(s, (uint32_t)L, mu);
+            double py = phi4_dot(phi + 4u * (size_t)y, r);
+            double a = ((px * py) * k4) / rr;
+            if (a > 0.0) {
+                double u = (double)w[mu] * 0x1p-32;
+                if (u < 1.0 - orc_phi4_expm(a)) b |= (uint8_t)(1u << mu);
+            }
+        }
+        bonds[s] = b;
+    }
+}
+
+/* Clusters: connected components of the bonds, labelled by their smallest
+ * site (the same union-find as the 2D oracle). */
+void orc_phi4_label(int32_t D, int32_t L, const uint8_t *bonds, uint32_t *labels)
+{
+    uint32_t n = phi4_sites(D, L);
+    for (uint32_t s = 0; s < n; ++s) labels[s] = s;
+    for (uint32_t s = 0; s < n; ++s)
+        for (int32_t mu = 0; mu < D; ++mu)
+            if (bonds[s] & (1u << mu)) uf_union(labels, s, phi4_step(s, (uint32_t)L, mu));
+    for (uint32_t s = 0; s < n; ++s) labels[s] = uf_find(labels, s);
+}
+
+/* Each cluster is reflected (eq. 3) with probability 1/2, independently. */
+int32_t orc_phi4_flip(uint64_t seed, uint32_t t, uint32_t root)
+{
+    uint32_t r[4];
+    philox_seed(seed, root >> 7, t, 6u, r);
+    return (int32_t)((r[(root >> 5) & 3u] >> (root & 31u)) & 1u);
+}
+
+void orc_phi4_reflect(int32_t D, int32_t L, uint64_t seed, uint32_t t, const uint32_t *labels,
+                      double *phi)
+{
+    uint32_t n = phi4_sites(D, L);
+    double r[4], rr;
+    orc_phi4_direction(seed, t, r, &rr);
+    for (uint32_t s = 0; s < n; ++s) {
+        if (!orc_phi4_flip(seed, t, labels[s])) continue;
+        double *f = phi + 4u * (size_t)s;
+        double c = (2.0 * phi4_dot(f, r)) / rr;
+        for (int a = 0; a < 4; ++a) f[a] = f[a] - c * r[a];
+    }
+}
+
+/* Measurement of a configuration and statistics of the clusters that made
+ * it; the derived doubles are computed from the exact integer sums. */
+void orc_phi4_observe(int32_t D, int32_t L, double kappa, uint64_t sweep, const double *phi,
+                      const uint32_t *labels, orc_phi4_obs *rec)
+{
+    uint32_t n = phi4_sites(D, L);
+    int64_t e = 0, m[4] = {0, 0, 0, 0};
+    for (uint32_t s = 0; s < n; ++s) {
+        const double *f = phi + 4u * (size_t)s;
+        for (int32_t mu = 0; mu < D; ++mu) {
+            const double *g = phi + 4u * (size_t)phi4_step(s, (uint32_t)L, mu);
+            e += (int64_t)rint(phi4_dot(f, g) * 0x1p32);
+        }
+        for (int a = 0; a < 4; ++a) m[a] += (int64_t)rint(f[a] * 0x1p32);
+    }
+    memset(rec, 0, sizeof(*rec));
+    rec->sweep = sweep;
+    rec->e_fix = e;
+    rec->action = -(2.0 * kappa) * ((double)e * 0x1p-32);
+    double ms = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        rec->m_fix[a] = m[a];
+        double ma = (double)m[a] * 0x1p-32;
+        ms = ms + ma * ma;
+    }
+    rec->m_abs = sqrt(ms);
+    if (labels) {
+        orc_obs c;
+        memset(&c, 0, sizeof(c));
+        cluster_stats(n, labels, &c, NULL);
+        rec->n_clusters = c.n_clusters;
+        rec->max_cluster = c.max_cluster;
+        rec->sum_sq_sizes = c.sum_sq_sizes;
+        memcpy(rec->hist_log2, c.hist_log2, sizeof(rec->hist_log2));
+    }
+}
+
+/* One multicluster update t: direction, bonds, clusters, reflections, record. */
+int orc_phi4_sweep(int32_t D, int32_t L, double kappa, uint64_t seed, uint32_t t, double *phi,
+                   uint32_t *labels, uint8_t *bonds, orc_phi4_obs *rec)
+{
+    uint32_t n = phi4_sites(D, L);
+    uint8_t *b = bonds ? bonds : (uint8_t *)malloc(n);
+    uint32_t *lab = labels ? labels : (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!b || !lab) {
+        if (!bonds) free(b);
+        if (!labels) free(lab);
+        return -1;
+    }
+    orc_phi4_bonds(D, L, kappa, seed, t, phi, b);
+    orc_phi4_label(D, L, b, lab);
+    orc_phi4_reflect(D, L, seed, t, lab, phi);
+    if (rec) orc_phi4_observe(D, L, kappa, t, phi, lab, rec);
+    if (!bonds) free(b);
+    if (!labels) free(lab);
+    return 0;
+}
+
+int orc_phi4_run(int32_t D, int32_t L, double kappa, uint64_t seed, uint32_t t0, int64_t count,
+                 double *phi, orc_phi4_obs *recs)
+{
+    uint32_t n = phi4_sites(D, L);
+    uint8_t *b = (uint8_t *)malloc(n);
+    uint32_t *lab = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!b || !lab) { free(b); free(lab); return -1; }
+    for (int64_t i = 0; i < count; ++i)
+        orc_phi4_sweep(D, L, kappa, seed, t0 + (uint32_t)i, phi, lab, b, recs ? &recs[i] : NULL);
+    free(b);
+    free(lab);
+    return 0;
+}

@@ -76,6 +76,36 @@ int orc_cubic_run(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed, uin
 int orc_cubic_chains(int32_t L, double J, uint32_t T, int32_t q, uint64_t seed0, int64_t nchains,
                      int32_t nsweeps, int64_t *e_out, int64_t *m_out);
 
+/* O(4) model with unit fields (phi^4 at lambda = infinity), D-dimensional
+ * periodic hypercube of side L, multicluster Wolff-embedding update. */
+typedef struct {
+    uint64_t sweep;
+    int64_t e_fix;          /* sum over the D N links of rint(2^32 phi_x . phi_y) */
+    double action;          /* -2 kappa e_fix 2^-32 (hopping part of the action)  */
+    int64_t m_fix[4];       /* sum over sites of rint(2^32 phi_x^a)               */
+    double m_abs;           /* |M| from m_fix                                     */
+    uint64_t n_clusters;
+    uint64_t max_cluster;
+    uint64_t sum_sq_sizes;
+    uint64_t hist_log2[33];
+} orc_phi4_obs;
+
+void orc_phi4_direction(uint64_t seed, uint32_t t, double r[4], double *rr);
+double orc_phi4_expm(double a);
+void orc_phi4_init(int32_t D, int32_t L, uint64_t seed, int32_t cold, double *phi);
+void orc_phi4_bonds(int32_t D, int32_t L, double kappa, uint64_t seed, uint32_t t,
+                    const double *phi, uint8_t *bonds);
+void orc_phi4_label(int32_t D, int32_t L, const uint8_t *bonds, uint32_t *labels);
+int32_t orc_phi4_flip(uint64_t seed, uint32_t t, uint32_t root);
+void orc_phi4_reflect(int32_t D, int32_t L, uint64_t seed, uint32_t t, const uint32_t *labels,
+                      double *phi);
+void orc_phi4_observe(int32_t D, int32_t L, double kappa, uint64_t sweep, const double *phi,
+                      const uint32_t *labels, orc_phi4_obs *rec);
+int orc_phi4_sweep(int32_t D, int32_t L, double kappa, uint64_t seed, uint32_t t, double *phi,
+                   uint32_t *labels, uint8_t *bonds, orc_phi4_obs *rec);
+int orc_phi4_run(int32_t D, int32_t L, double kappa, uint64_t seed, uint32_t t0, int64_t count,
+                 double *phi, orc_phi4_obs *recs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,7 @@ convention:
 from __future__ import annotations
 
 import itertools
+import math
 from collections import deque
 from decimal import Decimal, getcontext
 
@@ -263,3 +264,44 @@ def chi2_pvalue(observed, expected, min_expected: float = 5.0):
 
 def all_subsets(n):
     return itertools.product((0, 1), repeat=n)
+
+
+# ------------------------------------------------------- O(4) ring (exact)
+def o4_ring_link_energy(beta: float, L: int, lmax: int = 80) -> float:
+    """<u_i . u_{i+1}> on a periodic ring of L unit 4-vectors with weight
+    exp(beta sum_i u_i . u_{i+1}) and the uniform measure on S^3.
+
+    Transfer matrix: by the Funk-Hecke theorem the kernel exp(beta u . v)
+    acts on the degree-l harmonics of S^3 (multiplicity (l+1)^2) with
+    eigenvalue lambda_l = 2 I_{l+1}(beta) / beta (normalised measure), so
+    Z = sum_l (l+1)^2 lambda_l^L and <u . v> = (1/L) d ln Z / d beta, with
+    I_nu' = (I_{nu-1} + I_{nu+1}) / 2.  Scaled Bessel functions keep the
+    terms finite; the common factor e^beta cancels in the ratio."""
+    from scipy.special import ive
+
+    lam0 = 2.0 * ive(1, beta) / beta
+    num = den = 0.0
+    for l in range(lmax):
+        nu = l + 1
+        i_nu = ive(nu, beta)
+        d_nu = 0.5 * (ive(nu - 1, beta) + ive(nu + 1, beta))
+        lam = 2.0 * i_nu / beta
+        # derivative of the scaled eigenvalue plus the e^beta factor's share
+        dlam = 2.0 * d_nu / beta - 2.0 * i_nu / beta ** 2 - lam
+        w = (l + 1) ** 2
+        ratio = lam / lam0
+        den += w * ratio ** L
+        num += w * L * ratio ** (L - 1) * dlam / lam0
+    # the scaled eigenvalues are e^-beta lambda_l: add back d(beta)/d(beta) = 1 per link
+    return num / den / L + 1.0
+
+
+def o4_link_density_mean(b: float) -> float:
+    """Mean of t = u . v for two unit 4-vectors with weight exp(b t): the
+    relative angle of uniform vectors has density (2/pi) sqrt(1 - t^2);
+    by quadrature."""
+    from scipy.integrate import quad
+
+    w = lambda t: math.sqrt(1.0 - t * t) * math.exp(b * (t - 1.0))
+    z = quad(w, -1.0, 1.0)[0]
+    return quad(lambda t: t * w(t), -1.0, 1.0)[0] / z

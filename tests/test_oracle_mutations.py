@@ -13,6 +13,7 @@ import oracle
 import test_oracle_pins as pins
 import test_oracle_potts as potts
 import test_oracle_cubic as cubic
+import test_oracle_phi4 as phi4
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "sw_oracle.c")
 BETA_C = pins.BETA_C
@@ -72,6 +73,23 @@ MUTANTS = [
      "for (int32_t k = 0; k < q; ++k)\n            if (count[k] > m) m = count[k];",
      "for (int32_t k = 0; k < q - 1; ++k)\n            if (count[k] > m) m = count[k];",
      [lambda: cubic.test_potts_m_sum_is_the_largest_population(3)]),
+    ("phi4 bond with 2 kappa", "double k4 = 4.0 * kappa;", "double k4 = 2.0 * kappa;",
+     [lambda: phi4.test_ring_energy_exact(8, 1.0), phi4.test_bond_rule_keying_and_probability]),
+    ("phi4 projection not divided by r.r", "double a = ((px * py) * k4) / rr;", "double a = (px * py) * k4;",
+     [lambda: phi4.test_ring_energy_exact(3, 0.3), phi4.test_bond_rule_keying_and_probability]),
+    ("phi4 reflection without the factor 2", "double c = (2.0 * phi4_dot(f, r)) / rr;",
+     "double c = phi4_dot(f, r) / rr;", [phi4.test_reflection_of_whole_clusters]),
+    ("phi4 exp drops the last Taylor term", "for (int j = 13; j >= 1; --j) {", "for (int j = 13; j >= 2; --j) {",
+     [phi4.test_expm_matches_library_exp]),
+    ("phi4 reflection bit from word 0", "return (int32_t)((r[(root >> 5) & 3u] >> (root & 31u)) & 1u);",
+     "return (int32_t)((r[0] >> (root & 31u)) & 1u);", [phi4.test_reflection_of_whole_clusters]),
+    ("phi4 neighbour step goes backwards", "return x + 1u == L ? s - x * stride : s + stride;",
+     "return x == 0u ? s + (L - 1u) * stride : s - stride;",
+     [lambda: phi4.test_labels_are_min_site_components(4, 3), phi4.test_record_sums]),
+    ("phi4 hot start not normalised", "for (int a = 0; a < 4; ++a) f[a] = v[a] / len;",
+     "for (int a = 0; a < 4; ++a) f[a] = v[a];", [phi4.test_hot_and_cold_start]),
+    ("phi4 bond keyed by the sweep of the direction", "philox_seed(seed, s, t, 7u, w);",
+     "philox_seed(seed, s, t, 5u, w);", [phi4.test_bond_rule_keying_and_probability]),
 ]
 
 

@@ -112,6 +112,7 @@ def cpu_baseline(args):
             "L64_beta_c_1000_sweeps_1_core": legs["L64"],
             "L1024_three_betas_1_core": legs["L1024"],
             "grid_256_replicas_all_cores": legs["grid"],
+            "phi4_L28_kappa_0.304_1_core": legs["phi4_L28"],
         },
         "usable_host_cores": legs["usable_cores"],
     }
@@ -325,6 +326,50 @@ def serving(args):
     }
 
 
+# The paper's phi^4 timing experiment (its Sec. 5 table): 10^4 multicluster
+# updates at kappa = 0.304 on L^4 lattices, GPU minutes on its Tesla P100.
+# Context only: other hardware, other code.
+PAPER_PHI4_GPU_MINUTES = {16: 0.186, 20: 0.305, 24: 0.619, 28: 1.188}
+PHI4_KAPPA = 0.304
+# Algorithmic bytes per site and update of the five phi^4 kernels: fields
+# 32 B in and projection 8 B, parent and size out (projections); five
+# projections in (bonds); root in and out (flatten); fields in and out,
+# root and projection in (reflection); five fields, root and size in (record).
+PHI4_BYTES_PER_SITE = (32 + 8 + 4 + 4) + 40 + 8 + (32 + 32 + 4 + 8) + (5 * 32 + 8)
+
+
+def phi4(args):
+    """The 4D O(4) phi^4 multicluster update (unit fields) at kappa = 0.304
+    on the paper's lattice sides, hot start; per-kernel times from the
+    measurement entry point; the paper's P100 times for context."""
+    import paper_2302_14720_amd as sw
+
+    out = {"kappa": PHI4_KAPPA, "unit": "site-updates/s", "rows": []}
+    for L, paper_min in PAPER_PHI4_GPU_MINUTES.items():
+        N = L ** 4
+        p = sw.Phi4(L, PHI4_KAPPA, 6000 + L)
+        p.sweep(20)
+        p.sync()
+        t0 = time.perf_counter()
+        p.sweep(args.phi4_steps)
+        p.sync()
+        dt = time.perf_counter() - t0
+        prof = p.profile(20)
+        rec = p.series(p.next_sweep - 1, 1)[0]
+        p.close()
+        rate = N * args.phi4_steps / dt
+        ms = dt * 1e3 / args.phi4_steps
+        paper_ms = paper_min * 60e3 / 1e4
+        out["rows"].append({
+            "L": L, "sites": N, "sweeps": args.phi4_steps, "value": rate, "ms_per_step": ms,
+            "kernel_ms": prof, "roofline": hbm_fields(rate, PHI4_BYTES_PER_SITE),
+            "last_action_per_link": float(rec["action"]) / (4 * N),
+            "paper_p100_ms_per_update": paper_ms, "ratio_to_paper": paper_ms / ms})
+        print(f"[bench] phi4 L={L}: {rate:.4g} site-updates/s, {ms * 1e3:.1f} us per update "
+              f"(paper on P100: {paper_ms * 1e3:.0f} us), kernel ms {prof}", file=sys.stderr, flush=True)
+    return out
+
+
 def serving_saturated(args):
     """Serving capacity: every job is queued at time 0 (the queue is never
     empty while jobs remain), so the GPU is never waiting for arrivals; job
@@ -458,6 +503,8 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the serving leg, jobs/s")
     ap.add_argument("--serve-sat-jobs", type=int, default=64,
                     help="jobs of the saturated serving leg, all queued at once (0 = skip)")
+    ap.add_argument("--phi4-steps", type=int, default=500,
+                    help="timed multicluster updates per lattice side of the phi^4 leg (0 = skip)")
     ap.add_argument("--cpu-l1024-sweeps", type=int, default=20,
                     help="oracle sweeps per temperature of the L = 1024 CPU-baseline leg")
     ap.add_argument("--cpu-grid-sweeps", type=int, default=10,
@@ -607,6 +654,7 @@ def main() -> int:
         "serving_saturated": serving_saturated(args) if args.serve_sat_jobs > 0 else None,
         "potts_tile": potts_tile(args) if args.potts_steps > 0 else None,
         "cubic": cubic(args) if args.cubic_steps > 0 else None,
+        "phi4": phi4(args) if args.phi4_steps > 0 else None,
         "paper_table": paper_table(args) if args.paper_sweeps > 0 else None,
         "label_equivalence": label_equivalence(args, value) if args.le_steps > 0 else None,
     }

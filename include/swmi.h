@@ -407,6 +407,106 @@ int sw_server_status(sw_server *server, int32_t *queued, int32_t *active, size_t
 /* Destroys the server and every job (waits for the stream first). */
 void sw_server_destroy(sw_server *server);
 
+/* ------------------------------------------------------------- phi^4
+ * The paper's second workload (Sec. 3): the O(4)-symmetric phi^4 theory on
+ * the periodic L^4 lattice, one multicluster update of the Wolff embedding
+ * per sweep.  The paper gives the bond probability (eq. 2) and the cluster
+ * reflection (eq. 3) but neither the self-coupling lambda nor the radial
+ * update; here the fields are unit 4-vectors (the lambda -> infinity
+ * limit), whose weight exp(2 kappa sum_<xy> phi_x . phi_y) the cluster
+ * update samples on its own.
+ *
+ * Conventions: site x = ((x3 L + x2) L + x1) L + x0, periodic; each site owns
+ * the links to x + mu-hat, mu = 0..3 (4N links).  Fields are 4 doubles per
+ * site (x-major, component fastest).  Sweep t:
+ *   direction   the first of up to 64 candidates v = ((w_a + 0.5) 2^-31 - 1),
+ *               w = Philox({k, t, 5, 0}), k = 0, 1, ..., with
+ *               rr = ((v0 v0 + v1 v1) + v2 v2) + v3 v3 < 1; r = v (not
+ *               normalised); (1, 0, 0, 0) if none
+ *   projection  p_x = ((phi0 r0 + phi1 r1) + phi2 r2) + phi3 r3
+ *   bond (eq. 2) link (x, mu), y = x + mu-hat: a = ((p_x p_y) (4 kappa)) / rr;
+ *               bonded iff a > 0 and w 2^-32 < 1 - E(a), w = word mu of
+ *               Philox({x, t, 7, 0}); E(a) evaluates exp(-a): halve a to
+ *               b <= 1/8 (k times), q = 1, q = 1 - (q b) (1/j) for j = 13..1,
+ *               then square q k times
+ *   clusters    connected components, labelled by their smallest site
+ *   reflection  (eq. 3) a cluster whose smallest site r has bit r mod 128 of
+ *               Philox({r >> 7, t, 6, 0}) set: phi -= ((2 p_x) / rr) r
+ *   hot start   site x: first of up to 64 candidates from Philox({x, k, 8, 0})
+ *               inside the unit ball, divided by sqrt(vv); cold: (1, 0, 0, 0)
+ * All double arithmetic is IEEE-754, one correctly rounded operation at a
+ * time in the order written, so results are reproducible bit for bit.
+ * Records: exact int64 sums in units of 2^-32 (each term rounded to the
+ * nearest integer multiple first), so they do not depend on summation order. */
+typedef struct sw_phi4 sw_phi4;
+
+typedef struct {
+    uint64_t sweep;          /* sweep index t                                   */
+    int64_t e_fix;           /* sum over the 4N links of rint(2^32 phi_x . phi_y) */
+    double action;           /* -2 kappa e_fix 2^-32: the hopping action        */
+    int64_t m_fix[4];        /* sum over sites of rint(2^32 phi_x^a)            */
+    double m_abs;            /* |M| = sqrt(sum_a (m_fix[a] 2^-32)^2)            */
+    uint64_t n_clusters;     /* clusters of sweep t                             */
+    uint64_t max_cluster;
+    uint64_t sum_sq_sizes;
+    uint64_t hist_log2[33];  /* clusters with size in [2^k, 2^(k+1))            */
+} sw_phi4_obs;
+
+/* Device bytes of a phi^4 sim of side L with `ring` records (0 = 4096); 0
+ * for L outside [2, 64] or a bad ring. */
+size_t sw_phi4_workspace_bytes(int32_t L, int64_t ring);
+
+/* Creates a phi^4 sim of side L (2..64, N = L^4 sites), hopping parameter
+ * kappa in [0, 4] (the paper's runs use 0.304), seed, init (SW_INIT_HOT:
+ * fields uniform on the unit sphere; SW_INIT_COLD: (1, 0, 0, 0)), t = 0.
+ * dev_workspace: NULL (the library allocates) or a 256-byte-aligned device
+ * buffer of >= sw_phi4_workspace_bytes(L, ring) bytes kept alive by the
+ * caller; hip_stream: the stream for all work (NULL with dev_workspace NULL:
+ * the library creates one).  SW_EINVAL / SW_ENOMEM / SW_EHIP as for
+ * sw_create_ex. */
+int sw_phi4_create(int32_t L, double kappa, uint64_t seed, int32_t init, int64_t ring, void *dev_workspace,
+                   size_t ws_bytes, void *hip_stream, sw_phi4 **out);
+
+/* Re-initialises the fields and sets t = 0. */
+int sw_phi4_reset(sw_phi4 *sim, int32_t init);
+
+/* Enqueues n >= 0 multicluster updates (Sec. 3) and returns without waiting. */
+int sw_phi4_sweep(sw_phi4 *sim, int64_t n);
+
+/* Waits for all enqueued work. */
+int sw_phi4_sync(sw_phi4 *sim);
+
+/* Measurement aid: n >= 1 updates exactly as sw_phi4_sweep, launched kernel
+ * by kernel with HIP events on the sim's stream; ms[0..4] receive the mean
+ * milliseconds of the five kernels (projections, bonds and unions,
+ * flattening and sizes, reflections, measurement and record); nk >= 5. */
+int sw_phi4_profile(sw_phi4 *sim, int64_t n, double *ms, int32_t nk);
+
+/* Records first .. first+count-1 (Sec. 3 updates; measured after each) into
+ * host memory (waits); SW_ERANGE unless they ran since the last create /
+ * reset / set_field and are still held in the ring. */
+int sw_phi4_series(sw_phi4 *sim, int64_t first, int64_t count, sw_phi4_obs *out);
+
+/* Fields to host memory, n == 4 L^4 doubles. */
+int sw_phi4_get_field(sw_phi4 *sim, double *host, int64_t n);
+
+/* Replaces the fields (n == 4 L^4 finite doubles; the model's fields are
+ * unit vectors, which is not enforced) and makes next_sweep the index of the
+ * next sweep: an update depends only on the fields and on randomness keyed
+ * by (seed, sweep, site), so this resumes a chain or checks one update. */
+int sw_phi4_set_field(sw_phi4 *sim, const double *host, int64_t n, uint64_t next_sweep);
+
+/* Labels (smallest site of the cluster) of the last update's clusters,
+ * n == L^4; SW_ESTATE before the first update. */
+int sw_phi4_get_labels(sw_phi4 *sim, uint32_t *host, int64_t n);
+
+/* Number of sites L^4 / index of the next sweep; -1 for NULL. */
+int64_t sw_phi4_sites(const sw_phi4 *sim);
+int64_t sw_phi4_next_sweep(const sw_phi4 *sim);
+
+/* Destroys the sim (waits for its stream first); NULL is a no-op. */
+void sw_phi4_destroy(sw_phi4 *sim);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,8 @@ object:
   start, the first ``--l1024-sweeps`` of the 2000 sweeps each, one core;
 * ``L16384`` -- L = 16384, beta_c, hot start seed 4, ``--l16384-sweeps``
   sweeps, one core (the rate of the 200-sweep run is extrapolated from them);
+* ``phi4_L28`` -- the O(4) phi^4 multicluster update on the 28^4 lattice at
+  kappa = 0.304, hot start, ``--phi4-sweeps`` updates, one core;
 * ``grid``   -- the 256-replica temperature grid, ``--grid-sweeps`` sweeps
   of every replica, replicas spread over ``--cores`` worker processes (one
   sequential oracle each, largest replicas first onto the least loaded
@@ -57,6 +59,18 @@ def single(L: int, betas, seeds, sweeps: int) -> dict:
             "L": L, "betas": list(betas), "seeds": list(seeds), "sweeps_each": sweeps, "seconds": total}
 
 
+def phi4(L: int, kappa: float, seed: int, sweeps: int) -> dict:
+    """The O(4) phi^4 multicluster oracle on the L^4 lattice, one core."""
+    import oracle
+
+    phi = oracle.phi4_init(4, L, seed)
+    t0 = time.perf_counter()
+    oracle.phi4_run(4, L, kappa, seed, 0, sweeps, phi)
+    dt = time.perf_counter() - t0
+    return {"value": L ** 4 * sweeps / dt, "unit": "site-updates/s", "cores": 1, "L": L, "kappa": kappa,
+            "seed": seed, "sweeps": sweeps, "seconds": dt}
+
+
 def grid(sweeps: int, cores: int) -> dict:
     from paper_2302_14720_amd.replicas import grid_table
 
@@ -86,6 +100,7 @@ def main() -> int:
     ap.add_argument("--l1024-sweeps", type=int, default=20)
     ap.add_argument("--l16384-sweeps", type=int, default=1)
     ap.add_argument("--grid-sweeps", type=int, default=10)
+    ap.add_argument("--phi4-sweeps", type=int, default=5)
     args = ap.parse_args()
     usable = len(os.sched_getaffinity(0))
     cores = args.cores or min(usable, 16)
@@ -94,6 +109,7 @@ def main() -> int:
     out["L1024"] = single(1024, [0.30, BETA_C, 0.60], [10, 11, 12], args.l1024_sweeps)
     out["L16384"] = single(16384, [BETA_C], [4], args.l16384_sweeps)
     out["grid"] = grid(args.grid_sweeps, cores)
+    out["phi4_L28"] = phi4(28, 0.304, 6028, args.phi4_sweeps)
     print(json.dumps(out))
     return 0
 

@@ -140,6 +140,20 @@ _SIGNATURES = {
     "sw_server_release": (ctypes.c_int, [_P, ctypes.c_int64]),
     "sw_server_status": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "sw_server_destroy": (None, [_P]),
+    "sw_phi4_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
+    "sw_phi4_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32,
+                                      ctypes.c_int64, _P, ctypes.c_size_t, _P, _P]),
+    "sw_phi4_reset": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sw_phi4_sweep": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "sw_phi4_sync": (ctypes.c_int, [_P]),
+    "sw_phi4_profile": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_int32]),
+    "sw_phi4_series": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P]),
+    "sw_phi4_get_field": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "sw_phi4_set_field": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_uint64]),
+    "sw_phi4_get_labels": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "sw_phi4_sites": (ctypes.c_int64, [_P]),
+    "sw_phi4_next_sweep": (ctypes.c_int64, [_P]),
+    "sw_phi4_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -513,6 +527,103 @@ class Batch:
         h, self.handle = getattr(self, "handle", None), None
         if h:
             sw_batch_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# Layout of ``sw_phi4_obs`` (swmi.h).
+PHI4_OBS_DTYPE = np.dtype(
+    [
+        ("sweep", "<u8"),
+        ("e_fix", "<i8"),
+        ("action", "<f8"),
+        ("m_fix", "<i8", (4,)),
+        ("m_abs", "<f8"),
+        ("n_clusters", "<u8"),
+        ("max_cluster", "<u8"),
+        ("sum_sq_sizes", "<u8"),
+        ("hist_log2", "<u8", (33,)),
+    ]
+)
+PHI4_KERNELS = ("proj", "bond_union", "flatten", "reflect", "record")
+
+
+class Phi4:
+    """The O(4) phi^4 theory with unit fields on the L^4 periodic lattice,
+    one multicluster Wolff-embedding update per sweep (paper Sec. 3);
+    workspace and stream come from torch.  Fields are an (L^4, 4) float64
+    array."""
+
+    def __init__(self, L: int, kappa: float, seed: int = 0, *, init: int = SW_INIT_HOT, ring: int = 0,
+                 device=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("Phi4 needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.L, self.N = L, L ** 4
+        nbytes = int(lib().sw_phi4_workspace_bytes(L, ring))
+        h = ctypes.c_void_p()
+        if nbytes == 0:  # same validation as create, for the error message
+            _check(lib().sw_phi4_create(L, kappa, seed, init, ring, None, 0, None, ctypes.byref(h)))
+        dev = torch.device("cuda" if device is None else device)
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self._stream = torch.cuda.Stream(device=dev)
+        torch.cuda.current_stream(dev).synchronize()
+        _check(lib().sw_phi4_create(L, kappa, seed, init, ring, self._ws.data_ptr(), nbytes,
+                                    self._stream.cuda_stream, ctypes.byref(h)))
+        self.handle = h.value
+
+    def sweep(self, n: int) -> None:
+        _check(lib().sw_phi4_sweep(self.handle, n))
+
+    def sync(self) -> None:
+        _check(lib().sw_phi4_sync(self.handle))
+
+    def reset(self, init: int = SW_INIT_HOT) -> None:
+        _check(lib().sw_phi4_reset(self.handle, init))
+
+    def profile(self, n: int) -> dict:
+        ms = np.zeros(len(PHI4_KERNELS), dtype=np.float64)
+        _check(lib().sw_phi4_profile(self.handle, n, _ptr(ms), ms.size))
+        return dict(zip(PHI4_KERNELS, ms.tolist()))
+
+    def series(self, first: int, count: int) -> np.ndarray:
+        out = np.zeros(count, dtype=PHI4_OBS_DTYPE)
+        _check(lib().sw_phi4_series(self.handle, first, count, _ptr(out)))
+        return out
+
+    def field(self) -> np.ndarray:
+        out = np.empty((self.N, 4), dtype=np.float64)
+        _check(lib().sw_phi4_get_field(self.handle, _ptr(out), out.size))
+        return out
+
+    def set_field(self, phi: np.ndarray, next_sweep: int) -> None:
+        f = np.ascontiguousarray(phi, dtype=np.float64)
+        _check(lib().sw_phi4_set_field(self.handle, _ptr(f), f.size, next_sweep))
+
+    def labels(self) -> np.ndarray:
+        out = np.empty(self.N, dtype=np.uint32)
+        _check(lib().sw_phi4_get_labels(self.handle, _ptr(out), out.size))
+        return out
+
+    @property
+    def next_sweep(self) -> int:
+        return int(lib().sw_phi4_next_sweep(self.handle))
+
+    def close(self) -> None:
+        h, self.handle = getattr(self, "handle", None), None
+        if h:
+            lib().sw_phi4_destroy(h)
 
     def __del__(self):
         try:

@@ -7,11 +7,12 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sw_api.hip", "sw_kernels.hip", "sw_le.hip", "sw_server.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sw_api.hip", "sw_kernels.hip", "sw_le.hip", "sw_server.hip",
+                                                        "sw_phi4.hip")]
 LIB = os.path.join(HERE, "libswmi.so")
 
-# Packed FP32 instructions are disabled for all device code; the kernels
-# are integer-only, so this changes nothing they rely on.
+# Packed FP32 instructions are disabled for all device code (the Swendsen-
+# Wang kernels are integer-only; the phi^4 kernels compute in double).
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Wall", "-Wno-unused-function",

@@ -56,7 +56,7 @@ struct Dev {
     uint32_t *nk[2];      // [ntiles] number of nodes per tile, by parity
     uint32_t *key;        // [ntiles * kNodeSlots] smallest site of the node
     uint32_t *nsize;      // [ntiles * kNodeSlots] node size; cluster size at roots
-    int8_t *rspin;        // [ntiles * kNodeSlots] new spin, valid at root nodes
+    int8_t *rspin;        // [ntiles * kNodeSlots] new spin of each node's cluster
     uint8_t *edge;        // [ntiles][4][tw] node index of W, E, S, N edge sites
     uint64_t *xb;         // [ntiles][2] bonds leaving the tile: E (bit y), N (bit x)
     int32_t *tpart;       // [ntiles][kTilePart]

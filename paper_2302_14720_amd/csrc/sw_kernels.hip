@@ -26,6 +26,25 @@ __device__ __forceinline__ uint32_t hsb_le(uint32_t B, uint32_t x) {
     return 31u - (uint32_t)__clz((int)m);
 }
 
+// The TW-bit row mask whose 16-bit pieces (piece k at bit 16 k) are held by
+// the RPT = TW / 16 consecutive lanes of a tile row (a quad for TW = 64, a
+// pair for TW = 32): data-parallel moves within quads, no LDS.
+template <int K, int RPT>
+__device__ __forceinline__ uint32_t row_piece(uint32_t v) {
+    constexpr int ctrl = RPT == 4 ? K * 0x55 : (K | (K << 2) | ((2 + K) << 4) | ((2 + K) << 6));
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xF, 0xF, false);
+}
+template <int TW>
+__device__ __forceinline__ typename RowOf<TW>::T row_gather(uint32_t piece) {
+    if constexpr (TW == 64) {
+        const uint64_t lo = row_piece<0, 4>(piece) | (row_piece<1, 4>(piece) << 16);
+        const uint64_t hi = row_piece<2, 4>(piece) | (row_piece<3, 4>(piece) << 16);
+        return lo | (hi << 32);
+    } else {
+        return row_piece<0, 2>(piece) | (row_piece<1, 2>(piece) << 16);
+    }
+}
+
 // Workgroup b runs on XCD b % 8; give each XCD a contiguous band of tiles so
 // that neighbouring tiles (which share halo rows and cache lines) meet in
 // the same L2.
@@ -85,15 +104,10 @@ __device__ __forceinline__ uint32_t lds_root_b(uint32_t *par, uint32_t a) {
 
 // Spin (+1/-1) encoded by a byte of the previous sweep's output that belongs
 // to tile `tile`: final spins are 0x01 / 0xFF, a code 2 + k refers to node k
-// of that tile, whose root's spin was fixed by k_roots.
-__device__ __forceinline__ int8_t resolve_byte(uint32_t b, uint32_t tile, const uint32_t *par_prev,
-                                               const int8_t *rspin, uint32_t nnodes) {
+// of that tile, whose cluster's new spin k_roots stored at the node.
+__device__ __forceinline__ int8_t resolve_byte(uint32_t b, uint32_t tile, const int8_t *nspin) {
     const uint32_t k = b - 2u;
-    if (k < 252u) {
-        uint32_t p = par_prev[tile * kNodeSlots + k];
-        p = p < nnodes ? p : 0u;
-        return rspin[p];
-    }
+    if (k < 252u) return nspin[tile * kNodeSlots + k];
     return (int8_t)b;
 }
 
@@ -113,13 +127,13 @@ __device__ __forceinline__ uint32_t byte_at(const uint4 &v, int q) {
 // the values of q <= 4.
 template <int TW> constexpr uint32_t potts_code() { return TW == 64 ? 4u : 8u; }
 
+// The node spins are loaded whether or not the node exists (every slot is
+// in bounds), so that this load does not wait for the node count.
 template <int TW, bool POTTS>
 __device__ __forceinline__ void load_table(const Dev &d, uint32_t tile, uint32_t pp, uint8_t *s_tab,
                                            uint32_t tid) {
     constexpr int NT = TW * TW / 16;
-    const uint32_t nnodes = d.ntiles * kNodeSlots;
     const uint32_t kprev = min(d.nk[pp][tile], 252u);
-    const uint32_t *par_prev = d.parent[pp];
     for (uint32_t b = tid; b < 256u; b += NT) {
         uint8_t val;
         uint32_t k;
@@ -130,11 +144,8 @@ __device__ __forceinline__ void load_table(const Dev &d, uint32_t tile, uint32_t
             val = b == 0xFFu ? 0u : 1u;
             k = b - 2u;
         }
-        if (k < kprev) {
-            uint32_t p = par_prev[tile * kNodeSlots + k];
-            p = p < nnodes ? p : 0u;
-            val = POTTS ? (uint8_t)((uint32_t)d.rspin[p] & 7u) : (d.rspin[p] > 0 ? 1u : 0u);
-        }
+        const int8_t ns = k < 252u ? d.rspin[tile * kNodeSlots + k] : (int8_t)0;
+        if (k < kprev) val = POTTS ? (uint8_t)((uint32_t)ns & 7u) : (ns > 0 ? 1u : 0u);
         s_tab[b] = val;
     }
 }
@@ -147,25 +158,18 @@ __device__ __forceinline__ uint32_t decode16(const uint4 &v, const uint8_t *s_ta
     return up;
 }
 
-__device__ __forceinline__ uint32_t decode16_remote(const uint4 &v, uint32_t tile, const uint32_t *par_prev,
-                                                    const int8_t *rspin, uint32_t nnodes) {
+__device__ __forceinline__ uint32_t decode16_remote(const uint4 &v, uint32_t tile, const int8_t *nspin) {
     uint32_t up = 0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-        up |= (uint32_t)(resolve_byte(byte_at(v, q), tile, par_prev, rspin, nnodes) > 0) << q;
+    for (int q = 0; q < 16; ++q) up |= (uint32_t)(resolve_byte(byte_at(v, q), tile, nspin) > 0) << q;
     return up;
 }
 
 // Potts value (0..7) of a byte of tile `tile`'s previous output.
 template <int TW>
-__device__ __forceinline__ uint32_t potts_byte(uint32_t b, uint32_t tile, const uint32_t *par_prev,
-                                               const int8_t *rspin, uint32_t nnodes) {
+__device__ __forceinline__ uint32_t potts_byte(uint32_t b, uint32_t tile, const int8_t *nspin) {
     const uint32_t k = b - potts_code<TW>();
-    if (k < 252u) {
-        uint32_t p = par_prev[tile * kNodeSlots + k];
-        p = p < nnodes ? p : 0u;
-        return (uint32_t)rspin[p] & 7u;
-    }
+    if (k < 252u) return (uint32_t)nspin[tile * kNodeSlots + k] & 7u;
     return b & 7u;
 }
 
@@ -182,12 +186,12 @@ __device__ __forceinline__ void decode16_potts(const uint4 &v, const uint8_t *s_
 }
 
 template <int TW>
-__device__ __forceinline__ void decode16_potts_remote(const uint4 &v, uint32_t tile, const uint32_t *par_prev,
-                                                      const int8_t *rspin, uint32_t nnodes, uint32_t pl[3]) {
+__device__ __forceinline__ void decode16_potts_remote(const uint4 &v, uint32_t tile, const int8_t *nspin,
+                                                      uint32_t pl[3]) {
     pl[0] = pl[1] = pl[2] = 0u;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const uint32_t x = potts_byte<TW>(byte_at(v, q), tile, par_prev, rspin, nnodes);
+        const uint32_t x = potts_byte<TW>(byte_at(v, q), tile, nspin);
         pl[0] |= (x & 1u) << q;
         pl[1] |= ((x >> 1) & 1u) << q;
         pl[2] |= (x >> 2) << q;
@@ -251,17 +255,15 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     // written, so the 64-wide Potts tile keeps its three planes in s_par
     constexpr bool UP_IN_PAR = POTTS && TW == 64;
     static_assert(!UP_IN_PAR || 3 * (TW + 1) * sizeof(Row) <= TW * PS * 4, "planes must fit in s_par");
-    __shared__ Row s_up_own[UP_IN_PAR ? 1 : NPL * (TW + 1)];
+    __shared__ Row s_up_own[POTTS && !UP_IN_PAR ? NPL * (TW + 1) : 1];
     Row *const s_up = UP_IN_PAR ? reinterpret_cast<Row *>(s_par) : s_up_own;
-    __shared__ Row s_ebnb[2 * TW];  // bond masks to E (rows 0..TW-1) and N (rows TW..2TW-1)
+    __shared__ Row s_ebnb[2 * TW];  // bond masks to E of every row (rows 0..TW-1)
     Row *const s_eb = s_ebnb;
-    Row *const s_nb = s_ebnb + TW;
     __shared__ Row s_fb[TW];
     __shared__ Row s_xn;
     __shared__ uint32_t s_eup[NPL * EW];
     __shared__ uint32_t s_xe[EW];
     __shared__ uint32_t s_bf[NW];
-    __shared__ uint32_t s_pf[NW];
     __shared__ uint8_t s_tab[256];
     __shared__ uint32_t s_hist[12];
     // root | size << 16 of each node; for 64-wide tiles it reuses the bond
@@ -269,7 +271,6 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     __shared__ uint32_t s_node_own[TW == 64 ? 1 : 4 * TW];
     uint32_t *const s_node = TW == 64 ? reinterpret_cast<uint32_t *>(s_ebnb) : s_node_own;
     __shared__ int32_t s_red[NWAVE][POTTS ? 8 : 4];
-    __shared__ uint32_t s_k;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t L = d.L, ntx = d.ntx;
@@ -279,9 +280,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     const uint32_t pc = (uint32_t)(tsw & 1u), pp = pc ^ 1u;
     const int8_t *__restrict__ sin = d.spins[pc];
     int8_t *__restrict__ sout = d.spins[pp];
-    const uint32_t *__restrict__ par_prev = d.parent[pp];
     uint32_t *__restrict__ par_cur = d.parent[pc];
-    const uint32_t nnodes = d.ntiles * kNodeSlots;
 
     const uint32_t ly = tid / RPT, seg = tid % RPT, x0 = seg * 16u;
     const uint32_t gy = ty * TW + ly, gx0 = tx * TW + x0;
@@ -291,10 +290,16 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     const uint32_t rowoff = 4u * rowbase;  // its byte offset
     const uint32_t srow = ly * TW;     // site index of the row's first site
 
+    // rows of the tile a wavefront holds; lanes of a wavefront's last row
+    // (Ising) decode the next row's spins themselves, the others take them
+    // from the lanes RPT above
+    constexpr uint32_t RPW = 64u / RPT;
+    const bool wlast = (ly % RPW) == RPW - 1u;
+
     // ---- issue the spin loads first, then build the node table
     const uint4 v = *reinterpret_cast<const uint4 *>(sin + (size_t)gy * L + gx0);
     uint4 vn = make_uint4(0u, 0u, 0u, 0u);
-    if (ly == TW - 1) {
+    if (POTTS ? ly == TW - 1 : wlast) {
         const uint32_t gyn = (gy + 1u == L) ? 0u : gy + 1u;
         vn = *reinterpret_cast<const uint4 *>(sin + (size_t)gyn * L + gx0);
     }
@@ -302,6 +307,21 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     if (seg == RPT - 1) {
         const uint32_t gxe = (gx0 + 16u == L) ? 0u : gx0 + 16u;
         ve = (uint8_t)sin[(size_t)gy * L + gxe];
+    }
+    // the bond words of this lane's 16 sites (Sec. 2.1), drawn while the
+    // loads are in flight: bit 2j (2j+1) of rE / rN is the E / N edge of
+    // site 2j (2j+1) past the lane's first site, set iff its word is below T
+    uint32_t rE = 0u, rN = 0u;
+    {
+        const uint32_t c0 = (gy * L + gx0) >> 1;
+        const uint32_t T = d.T;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            uint32_t w0 = c0 + (uint32_t)j, w1 = t, w2 = 0u, w3 = 0u;
+            philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
+            rE |= ((uint32_t)(w0 < T) << (2 * j)) | ((uint32_t)(w2 < T) << (2 * j + 1));
+            rN |= ((uint32_t)(w1 < T) << (2 * j)) | ((uint32_t)(w3 < T) << (2 * j + 1));
+        }
     }
     load_table<TW, POTTS>(d, tile, pp, s_tab, tid);
 
@@ -340,43 +360,49 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     if (tid == 0) s_xn = 0;
     __syncthreads();
 
-    // ---- decode the incoming configuration to up-spin masks (Potts: bit
-    // planes of the values)
+    // ---- decode the incoming configuration (Sec. 2.5 measures it; Sec. 2.1
+    // bonds it).  Ising: the up-spin mask of the lane's 16 sites, of the 16
+    // sites above (lanes RPT further on, or decoded here by a wavefront's
+    // last row) and the east neighbour of its last site (the next lane, or
+    // the east tile).  Potts: three bit planes per row, through LDS.
     uint32_t up = 0u, pl[3] = {0u, 0u, 0u};
+    uint32_t upN = 0u, ebit = 0u;
     if constexpr (POTTS) {
         decode16_potts(v, s_tab, pl);
 #pragma unroll
         for (int b = 0; b < 3; ++b) reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[ly * RPT + seg] = (uint16_t)pl[b];
         if (ly == TW - 1) {
             uint32_t pn[3];
-            decode16_potts_remote<TW>(vn, north, par_prev, d.rspin, nnodes, pn);
+            decode16_potts_remote<TW>(vn, north, d.rspin, pn);
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[TW * RPT + seg] = (uint16_t)pn[b];
         }
         if (seg == RPT - 1) {
-            const uint32_t ev = potts_byte<TW>(ve, east, par_prev, d.rspin, nnodes);
+            const uint32_t ev = potts_byte<TW>(ve, east, d.rspin);
 #pragma unroll
             for (uint32_t b = 0; b < 3u; ++b)
                 if ((ev >> b) & 1u) atomicOr(&s_eup[b * EW + (ly >> 5)], 1u << (ly & 31u));
         }
+        __syncthreads();
     } else {
         up = decode16<TW>(v, s_tab);
-        reinterpret_cast<uint16_t *>(s_up)[ly * RPT + seg] = (uint16_t)up;
-        if (ly == TW - 1) {
-            const uint32_t upn = decode16_remote(vn, north, par_prev, d.rspin, nnodes);
-            reinterpret_cast<uint16_t *>(s_up)[TW * RPT + seg] = (uint16_t)upn;
-        }
-        if (seg == RPT - 1) {
-            if (resolve_byte(ve, east, par_prev, d.rspin, nnodes) > 0) atomicOr(&s_eup[ly >> 5], 1u << (ly & 31u));
-        }
+        const uint32_t upA = (uint32_t)__shfl_down((int)up, (int)RPT, 64);
+        const uint32_t upR = (uint32_t)__shfl_down((int)up, 1, 64);
+        if (wlast)
+            upN = ly == TW - 1 ? decode16_remote(vn, north, d.rspin) : decode16<TW>(vn, s_tab);
+        else
+            upN = upA;
+        ebit = seg == RPT - 1 ? (uint32_t)(resolve_byte(ve, east, d.rspin) > 0) : (upR & 1u);
     }
-    __syncthreads();
 
     // ---- bonds (Sec. 2.1) and energy / magnetisation of the incoming spins
-    // (Potts: equal pairs and value populations)
+    // (Potts: equal pairs and value populations); then every site points at
+    // the start of its row run (the row's E bonds are gathered from its RPT
+    // lanes), and the bond masks go to LDS for the vertical unions
     int32_t e_part, m_part;
     uint32_t cpk[4] = {0u, 0u, 0u, 0u};
+    uint32_t bE, bN;
     {
         uint32_t eqE, eqN;
         if constexpr (POTTS) {
@@ -385,8 +411,8 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
             for (int b = 0; b < 3; ++b) {
                 const Row rowv = s_up[b * (TW + 1) + ly];
                 const uint32_t pN = (uint32_t)(s_up[b * (TW + 1) + ly + 1] >> x0) & 0xFFFFu;
-                const uint32_t ebit = (s_eup[b * EW + (ly >> 5)] >> (ly & 31u)) & 1u;
-                const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
+                const uint32_t eb = (s_eup[b * EW + (ly >> 5)] >> (ly & 31u)) & 1u;
+                const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : eb;
                 const uint32_t pE = (pl[b] >> 1) | (nxt << 15);
                 dE |= pl[b] ^ pE;
                 dN |= pl[b] ^ pN;
@@ -397,27 +423,14 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
             m_part = 0;
             potts_counts(pl, cpk);
         } else {
-            const Row rowv = s_up[ly];
-            const uint32_t upN = (uint32_t)(s_up[ly + 1] >> x0) & 0xFFFFu;
-            const uint32_t ebit = (s_eup[ly >> 5] >> (ly & 31u)) & 1u;
-            const uint32_t nxt = (x0 + 16u < (uint32_t)TW) ? ((uint32_t)(rowv >> (x0 + 16u)) & 1u) : ebit;
-            const uint32_t upE = (up >> 1) | (nxt << 15);
+            const uint32_t upE = (up >> 1) | (ebit << 15);
             eqE = ~(up ^ upE) & 0xFFFFu;
             eqN = ~(up ^ upN) & 0xFFFFu;
             e_part = 2 * (__popc(eqE) + __popc(eqN)) - 32;
             m_part = 2 * __popc(up) - 16;
         }
-        uint32_t rE = 0u, rN = 0u;
-        const uint32_t c0 = (gy * L + gx0) >> 1;
-        const uint32_t T = d.T;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            uint32_t w0 = c0 + (uint32_t)j, w1 = t, w2 = 0u, w3 = 0u;
-            philox10(w0, w1, w2, w3, d.seed_lo, d.seed_hi);
-            rE |= ((uint32_t)(w0 < T) << (2 * j)) | ((uint32_t)(w2 < T) << (2 * j + 1));
-            rN |= ((uint32_t)(w1 < T) << (2 * j)) | ((uint32_t)(w3 < T) << (2 * j + 1));
-        }
-        uint32_t bE = eqE & rE, bN = eqN & rN;
+        bE = eqE & rE;
+        bN = eqN & rN;
         if (seg == RPT - 1) {
             if (bE >> 15) atomicOr(&s_xe[ly >> 5], 1u << (ly & 31u));
             bE &= 0x7FFFu;
@@ -427,22 +440,15 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
             bN = 0u;
         }
         reinterpret_cast<uint16_t *>(s_eb)[ly * RPT + seg] = (uint16_t)bE;
-        reinterpret_cast<uint16_t *>(s_nb)[ly * RPT + seg] = (uint16_t)bN;
     }
-    __syncthreads();
-
-    // ---- row runs: every site points at the start of its run
-    const Row E0 = s_eb[ly];
+    const Row E0 = row_gather<TW>(bE);  // this row's E bonds inside the tile
+    const Row V = row_gather<TW>(bN);   // this row's N bonds inside the tile
     const Row B0 = (Row)~(Row)(E0 << 1);
     const uint32_t st = (uint32_t)(B0 >> x0) & 0xFFFFu;
     const uint32_t rs0 = rowoff + 4u * hsb_le(B0, x0);  // byte offset of the run start at x0
-    uint32_t r = 0u;  // representative vertical bonds of this segment
-    if (ly + 1u < (uint32_t)TW) {
-        const Row V = s_nb[ly];
-        const Row E1 = s_eb[ly + 1];
-        const Row R = V & (Row)~(Row)((V << 1) & (E0 << 1) & (E1 << 1));
-        r = (uint32_t)(R >> x0) & 0xFFFFu;
-    }
+    // the 64-wide Potts tile keeps its planes in s_par: wait until every
+    // lane has read them
+    if constexpr (UP_IN_PAR) __syncthreads();
     {
         uint32_t cur = rs0;
 #pragma unroll
@@ -458,7 +464,15 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     // vertical bonds that connect the same pair of runs; each wavefront lists
     // its unions in the high halves of its own rows' words and then works
     // through the list 64 at a time, so that lanes with many bonds do not
-    // hold up the rest.
+    // hold up the rest.  The list is private to the wavefront; the compare-
+    // and-swap of a union keeps a word's high half and retries if it
+    // changed, so other wavefronts may build or clear their lists meanwhile.
+    uint32_t r = 0u;  // representative vertical bonds of this segment
+    if (ly + 1u < (uint32_t)TW) {
+        const Row E1 = s_eb[ly + 1];
+        const Row R = V & (Row)~(Row)((V << 1) & (E0 << 1) & (E1 << 1));
+        r = (uint32_t)(R >> x0) & 0xFFFFu;
+    }
     const uint32_t lane = tid & 63u;
     const uint32_t wbase = (tid >> 6) * (64u / RPT) * PS;
     uint32_t nlist;
@@ -483,7 +497,8 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
             ++w;
         }
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     for (uint32_t k = lane; k < nlist; k += 64u) {
         const uint32_t n = lds_load(&s_par[wbase + k]) >> 16;
         __hip_atomic_fetch_and(&s_par[wbase + k], 0xFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -493,9 +508,12 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
 
     // ---- cluster sizes.  Every run start in this lane's 16 sites is pointed
     // at its root and adds the whole run's length (read off the row's
-    // run-start mask; the run may go on into the next lanes' sites).
+    // run-start mask; the run may go on into the next lanes' sites).  Runs
+    // that touch the tile edge mark their root: the S and N rows, the first
+    // run of every row (x = 0) and the run holding x = TW - 1.
     uint32_t rootmask = 0u;
     {
+        const bool edge_row = ly == 0u || ly == TW - 1u;
         const Row after = (Row)(B0 >> 1);  // bit x: a run starts at x + 1
         // lengths of consecutive runs with the same root are summed in a
         // register (at most TW per lane) and added with one atomic
@@ -510,6 +528,10 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
                 __hip_atomic_store(word_at(s_par, n), root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             else
                 rootmask |= 1u << i;
+            if (edge_row || (seg == 0u && i == 0u) || (seg == RPT - 1u && m == 0u)) {
+                const uint32_t rsite = root / 4u - root / (4u * PS);
+                atomicOr(&s_bf[rsite >> 5], 1u << (rsite & 31u));
+            }
             const Row nx = (Row)(after >> (x0 + i));  // bit j: the next run starts j + 1 sites on
             uint32_t len;
             if constexpr (TW == 64)
@@ -525,50 +547,42 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         if (acc_len != 0u)
             __hip_atomic_fetch_add(word_at(s_par, acc_root), acc_len << 16, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+        // a segment that starts inside a run which reaches the S or N edge,
+        // or (last segment of a row) holds no run start of its own
+        if (!(st & 1u) && (edge_row || (seg == RPT - 1u && st == 0u))) {
+            const uint32_t root = lds_root_b(s_par, rs0);
+            const uint32_t rsite = root / 4u - root / (4u * PS);
+            atomicOr(&s_bf[rsite >> 5], 1u << (rsite & 31u));
+        }
     }
     __syncthreads();
 
-    // ---- clusters that touch the tile edge: one edge site per thread marks
-    // its root (run starts now point at their roots)
-    for (uint32_t e = tid; e < 4u * (TW - 1u); e += NT) {
-        const uint32_t side = e / (TW - 1u), j = e % (TW - 1u);
-        // S row x = j, N row x = j + 1, W column y = j + 1, E column y = j
-        const uint32_t y = side == 0u ? 0u : side == 1u ? TW - 1u : side == 2u ? j + 1u : j;
-        const uint32_t x = side == 0u ? j : side == 1u ? j + 1u : side == 2u ? 0u : TW - 1u;
-        const uint32_t rs = s_par[y * PS + x] & 0xFFFFu;
-        const uint32_t root = *word_at(s_par, rs) & 0xFFFFu;
-        const uint32_t rsite = root / 4u - root / (4u * PS);
-        atomicOr(&s_bf[rsite >> 5], 1u << (rsite & 31u));
-    }
-    __syncthreads();
-
-    // ---- number the boundary clusters (nodes) in site order
-    if (tid < 64u) {
+    // ---- number the boundary clusters (nodes) in site order: every
+    // wavefront scans the marks itself, lane l holding the prefix of mark
+    // words (NW / 64) l .. (NW / 64) (l + 1) - 1
+    uint32_t pf_a, pf_b, n_nodes;
+    {
         uint32_t wa = 0u, wb = 0u, c;
         if constexpr (NW == 128) {
-            wa = s_bf[2 * tid];
-            wb = s_bf[2 * tid + 1];
+            wa = s_bf[2 * lane];
+            wb = s_bf[2 * lane + 1];
             c = __popc(wa) + __popc(wb);
         } else {
-            wa = tid < (uint32_t)NW ? s_bf[tid] : 0u;
+            wa = lane < (uint32_t)NW ? s_bf[lane] : 0u;
             c = __popc(wa);
         }
         uint32_t incl = c;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t n = __shfl_up(incl, o, 64);
-            if (tid >= (uint32_t)o) incl += n;
+            if (lane >= (uint32_t)o) incl += n;
         }
-        const uint32_t excl = incl - c;
-        if constexpr (NW == 128) {
-            s_pf[2 * tid] = excl;
-            s_pf[2 * tid + 1] = excl + __popc(wa);
-        } else {
-            if (tid < (uint32_t)NW) s_pf[tid] = excl;
-        }
-        if (tid == 63u) s_k = incl;
+        pf_a = incl - c;
+        pf_b = pf_a + __popc(wa);
+        // at most 4 (TW - 1) boundary clusters; the bound keeps the node
+        // tables in their slots whatever the marks
+        n_nodes = min((uint32_t)__shfl((int)incl, 63, 64), 4u * ((uint32_t)TW - 1u));
     }
-    __syncthreads();
 
     // ---- roots: output byte into the root's word; node entries staged in
     // LDS; interior-cluster statistics (size classes 0-2 packed in one
@@ -579,7 +593,16 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
         const uint32_t bfw = s_bf[sbase >> 5];
         const uint32_t bsh = sbase & 31u;
         const uint32_t bmask = (bfw >> bsh) & 0xFFFFu;
-        const uint32_t kbase = s_pf[sbase >> 5] + __popc(bfw & ((1u << bsh) - 1u));
+        // prefix of mark word sbase >> 5, held by lane (sbase >> 5) / (NW / 64)
+        uint32_t pf;
+        if constexpr (NW == 128) {
+            const uint32_t qa = (uint32_t)__shfl((int)pf_a, (int)((sbase >> 5) >> 1), 64);
+            const uint32_t qb = (uint32_t)__shfl((int)pf_b, (int)((sbase >> 5) >> 1), 64);
+            pf = ((sbase >> 5) & 1u) ? qb : qa;
+        } else {
+            pf = (uint32_t)__shfl((int)pf_a, (int)(sbase >> 5), 64);
+        }
+        const uint32_t kbase = pf + __popc(bfw & ((1u << bsh) - 1u));
         const uint32_t fl = POTTS ? 0u : (uint32_t)(s_fb[ly] >> x0) & 0xFFFFu;
         while (rootmask) {
             const uint32_t q = (uint32_t)__ffs((int)rootmask) - 1u;
@@ -610,7 +633,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     }
     __syncthreads();
     // node tables of this tile, written in node order
-    for (uint32_t k = tid; k < s_k; k += NT) {
+    for (uint32_t k = tid; k < n_nodes; k += NT) {
         const uint32_t e = s_node[k], site = e & 0xFFFFu, node = tile * kNodeSlots + k;
         d.key[node] = (ty * TW + site / TW) * L + tx * TW + site % TW;
         d.nsize[node] = e >> 16;
@@ -723,7 +746,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
                 tp[TP_CNT + k] = c;
             }
         }
-        d.nk[pc][tile] = s_k;
+        d.nk[pc][tile] = n_nodes;
         uint64_t xe = s_xe[0];
         if constexpr (TW == 64) xe |= (uint64_t)s_xe[1] << 32;
         d.xb[2u * tile] = xe;
@@ -1041,10 +1064,14 @@ __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
             const uint32_t q = (uint32_t)(i >= pre1) + (uint32_t)(i >= pre2) + (uint32_t)(i >= pre3);
             const uint32_t base = q == 0u ? 0u : q == 1u ? pre1 : q == 2u ? pre2 : pre3;
             const uint32_t node = (g0 + wv + 4u * q) * kNodeSlots + (i - base);
-            if (par[node] == node) {
+            // every node (flattened: its parent is its root) stores its
+            // cluster's new spin, drawn from the cluster's smallest site
+            const uint32_t root = par[node];
+            const uint32_t rkey = d.key[root];
+            d.rspin[node] = d.q ? potts_spin(rkey, t, d.q, d.seed_lo, d.seed_hi)
+                                : cluster_spin(rkey, t, d.seed_lo, d.seed_hi);
+            if (root == node) {
                 const uint32_t S = d.nsize[node];
-                d.rspin[node] = d.q ? potts_spin(d.key[node], t, d.q, d.seed_lo, d.seed_hi)
-                                    : cluster_spin(d.key[node], t, d.seed_lo, d.seed_hi);
                 ++n;
                 mx = max(mx, (uint64_t)S);
                 sq += (uint64_t)S * S;
@@ -1278,8 +1305,6 @@ __device__ __forceinline__ void resolve_body(const Dev &d, const uint32_t tile) 
     const uint64_t tsw = *d.tdev;
     const uint32_t pc = (uint32_t)(tsw & 1u), pp = pc ^ 1u;
     int8_t *sp = d.spins[pc];
-    const uint32_t *par_prev = d.parent[pp];
-    const uint32_t nnodes = d.ntiles * kNodeSlots;
     const uint32_t ly = tid / RPT, seg = tid % RPT, x0 = seg * 16u;
     const uint32_t gy = ty * TW + ly, gx0 = tx * TW + x0;
     const uint32_t east = ty * ntx + (tx + 1u == ntx ? 0u : tx + 1u);
@@ -1306,13 +1331,13 @@ __device__ __forceinline__ void resolve_body(const Dev &d, const uint32_t tile) 
         for (int b = 0; b < 3; ++b) reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[ly * RPT + seg] = (uint16_t)pl[b];
         if (ly == TW - 1) {
             uint32_t pn[3];
-            decode16_potts_remote<TW>(vn, north, par_prev, d.rspin, nnodes, pn);
+            decode16_potts_remote<TW>(vn, north, d.rspin, pn);
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 reinterpret_cast<uint16_t *>(s_up + b * (TW + 1))[TW * RPT + seg] = (uint16_t)pn[b];
         }
         if (seg == RPT - 1) {
-            const uint32_t ev = potts_byte<TW>(ve, east, par_prev, d.rspin, nnodes);
+            const uint32_t ev = potts_byte<TW>(ve, east, d.rspin);
 #pragma unroll
             for (uint32_t b = 0; b < 3u; ++b)
                 if ((ev >> b) & 1u) atomicOr(&s_eup[b * EW + (ly >> 5)], 1u << (ly & 31u));
@@ -1321,11 +1346,11 @@ __device__ __forceinline__ void resolve_body(const Dev &d, const uint32_t tile) 
         up = decode16<TW>(v, s_tab);
         reinterpret_cast<uint16_t *>(s_up)[ly * RPT + seg] = (uint16_t)up;
         if (ly == TW - 1) {
-            const uint32_t upn = decode16_remote(vn, north, par_prev, d.rspin, nnodes);
+            const uint32_t upn = decode16_remote(vn, north, d.rspin);
             reinterpret_cast<uint16_t *>(s_up)[TW * RPT + seg] = (uint16_t)upn;
         }
         if (seg == RPT - 1) {
-            if (resolve_byte(ve, east, par_prev, d.rspin, nnodes) > 0) atomicOr(&s_eup[ly >> 5], 1u << (ly & 31u));
+            if (resolve_byte(ve, east, d.rspin) > 0) atomicOr(&s_eup[ly >> 5], 1u << (ly & 31u));
         }
     }
     __syncthreads();

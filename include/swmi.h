@@ -507,6 +507,26 @@ int64_t sw_phi4_next_sweep(const sw_phi4 *sim);
 /* Destroys the sim (waits for its stream first); NULL is a no-op. */
 void sw_phi4_destroy(sw_phi4 *sim);
 
+/* ---------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one sweep
+ * t of the L x L Ising lattice, exactly as sw_sweep runs sweep t of a sim
+ * created with (L, beta, J, seed) whose spins equal `spins` -- same kernels,
+ * same bits, same record.  spins: device pointer to N = L*L int8 spins
+ * (+1 / -1, site order s = y*L + x, 16-byte aligned), read as the incoming
+ * configuration and overwritten with the configuration sweep t leaves.
+ * rec: device pointer to one sw_obs (8-byte aligned), which receives record t.  hip_stream:
+ * the stream all work is enqueued on (NULL: the null stream); the call
+ * returns without waiting.  Nothing is allocated: every other buffer of the
+ * sweep lives in one static device array of 16 MiB per GPU, held until the
+ * process ends, so L is at most 2048 (SW_ERANGE above).  All calls on one
+ * GPU share that array: calls that overlap on one GPU (other streams or
+ * threads) race; calls on one stream are ordered.  SW_EINVAL for NULL or
+ * misaligned pointers and for L, beta or J outside their domain (as for
+ * sw_create), SW_EHIP if a launch fails. */
+int sw_sweep_noalloc(int32_t L, double beta, double J, uint64_t seed, uint64_t t, int8_t *spins,
+                     sw_obs *rec, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -154,6 +154,8 @@ _SIGNATURES = {
     "sw_phi4_sites": (ctypes.c_int64, [_P]),
     "sw_phi4_next_sweep": (ctypes.c_int64, [_P]),
     "sw_phi4_destroy": (None, [_P]),
+    "sw_sweep_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                        ctypes.c_uint64, _P, _P, _P]),
 }
 
 _lib = None
@@ -300,6 +302,15 @@ def sw_destroy(h: int) -> None:
 
 def sw_last_error() -> str:
     return lib().sw_last_error().decode()
+
+
+def sw_sweep_noalloc(L: int, beta: float, J: float, seed: int, t: int, spins_ptr: int, rec_ptr: int,
+                     stream_ptr: int = 0) -> None:
+    """Sweep t of the lattice whose int8 spins sit at device address
+    spins_ptr (overwritten in place); record t to the sw_obs at rec_ptr.
+    Allocates nothing (the library's static scratch holds every other
+    buffer); returns without waiting for the stream."""
+    _check(lib().sw_sweep_noalloc(L, beta, J, seed, t, spins_ptr or None, rec_ptr or None, stream_ptr or None))
 
 
 # ------------------------------------------------------------- batch calls

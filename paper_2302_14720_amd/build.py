@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sw_api.hip", "sw_kernels.hip", "sw_le.hip", "sw_server.hip",
-                                                        "sw_phi4.hip")]
+                                                        "sw_phi4.hip", "sw_noalloc.hip")]
 LIB = os.path.join(HERE, "libswmi.so")
 
 # Packed FP32 instructions are disabled for all device code (the Swendsen-

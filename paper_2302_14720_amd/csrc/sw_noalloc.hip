@@ -18,7 +18,7 @@
 
 namespace {
 
-constexpr size_t kScratchBytes = (size_t)32 << 20;  // covers every L <= 2048
+constexpr size_t kScratchBytes = (size_t)16 << 20;  // L = 2048 needs 12.7 MiB
 constexpr int32_t kNoallocMaxL = 2048;
 constexpr int kMaxDevices = 64;
 
@@ -73,15 +73,16 @@ extern "C" int sw_sweep_noalloc(int32_t L, double beta, double J, uint64_t seed,
                                 sw_obs *rec, void *hip_stream) {
     using namespace swmi;
     if (!spins || !rec) return fail(SW_EINVAL, "spins and rec must be device pointers");
-    if (L > kNoallocMaxL) return fail(SW_ERANGE, "L must be at most 2048 here (the static scratch holds 32 MiB)");
+    if (L > kNoallocMaxL) return fail(SW_ERANGE, "L must be at most 2048 here (the static scratch holds 16 MiB)");
     sw_config c;
     sw_config_init(&c, L, beta, J, seed);
     c.ring = 1;
     int rc = validate(&c);
     if (rc != SW_OK) return rc;
     const Layout lo = layout_of(c);
-    if (lo.total > kScratchBytes) return fail(SW_ERANGE, "lattice needs more than the 32 MiB static scratch");
+    if (lo.total > kScratchBytes) return fail(SW_ERANGE, "lattice needs more than the 16 MiB static scratch");
     if (((uintptr_t)spins % 16u) != 0u) return fail(SW_EINVAL, "spins must be 16-byte aligned");
+    if (((uintptr_t)rec % 8u) != 0u) return fail(SW_EINVAL, "rec must be 8-byte aligned");
     int device = -1;
     HIP_TRY(hipGetDevice(&device));
     void *base = nullptr;

@@ -119,9 +119,10 @@ def cpu_baseline(args):
 
 
 def batched_vs_plain(args):
-    """The 256-replica temperature grid swept as one batch (five launches per
-    sweep for all replicas) and as 256 plain sims (one sw_sweep per replica
-    per sweep, as a caller without batching would drive them)."""
+    """The 256-replica temperature grid swept as one batch (the kernels of a
+    sweep launched once per launch group for all replicas, tile width and
+    merge autotuned per lattice side) and as 256 plain sims (one sw_sweep(n)
+    per replica stream, and one sw_sweep(1) per replica per sweep)."""
     import torch
 
     import paper_2302_14720_amd as sw
@@ -131,10 +132,13 @@ def batched_vs_plain(args):
 
     L, beta, seed = grid_table(256, 1000)
     sites = int((L.astype("int64") ** 2).sum())
-    tile, tune_ms = autotune.tune_batch(L, beta, 1.0, seed, sweeps=10, use_cache=False)
-    print(f"[bench] batched: {len(L)} replicas, {sites} sites; autotuned tile {tile} ({tune_ms} ms/sweep)",
+    tiles, merges, tune_ms = autotune.tune_batch_per_side(L, beta, 1.0, seed, sweeps=10, use_cache=False)
+    choice = {int(side): {"tile": int(tiles[L == side][0]),
+                          "merge": "lds" if int(merges[L == side][0]) == sw.SW_MERGE_LDS else "global"}
+              for side in sorted(set(L.tolist()))}
+    print(f"[bench] batched: {len(L)} replicas, {sites} sites; autotuned per side {choice}",
           file=sys.stderr, flush=True)
-    b = sw.Batch(L, beta, 1.0, seed, tile=tile)
+    b = sw.Batch(L, beta, 1.0, seed, tiles=tiles, merge=merges)
     b.sweep(args.warmup)
     b.sync()
     t0 = time.perf_counter()
@@ -179,8 +183,9 @@ def batched_vs_plain(args):
     return {
         "workload": "256 replicas, L = {64,128,256,512,1024}[r mod 5], beta_k = 0.40 + 0.08 k/31 "
                     "(k = r // 8), seed 1000 + r, hot start, J = 1",
-        "replicas": len(L), "sites": sites, "tile": tile,
-        "autotune_ms_per_sweep": {str(k): v for k, v in tune_ms.items()},
+        "replicas": len(L), "sites": sites, "per_side": choice,
+        "autotune_ms_per_sweep": {f"L={k[0]}": {f"tile{t}_{'lds' if m == sw.SW_MERGE_LDS else 'global'}": v
+                                                for (t, m), v in ms.items()} for k, ms in tune_ms.items()},
         "value": bval, "unit": "site-updates/s", "sweeps": args.batch_steps,
         "ms_per_step": bdt * 1e3 / args.batch_steps,
         "plain": {"how": "256 plain sims, each on its own stream, one sw_sweep(n) call per replica",

@@ -255,15 +255,23 @@ const char *sw_last_error(void);
 
 /* ------------------------------------------------------------- batches
  * A batch advances n independent lattices (replicas) together: every kernel
- * of a sweep (Sec. 2) runs once over all replicas, so a sweep of the whole
- * batch costs five kernel launches (replayed from one captured graph)
- * instead of five per replica.  Replica r has its own L[r], beta[r], J[r],
+ * of a sweep (Sec. 2) runs once over all replicas of a launch group (the
+ * replicas with one tile width and model), so a sweep of the whole batch
+ * costs a handful of kernel launches (replayed from one captured graph)
+ * instead of six per replica.  The cross-tile merge of Sec. 2.3 runs either
+ * globally (four launches over all such replicas) or, for a replica of at
+ * most 16 tiles, entirely in one workgroup's LDS (one launch for all such
+ * replicas: SW_MERGE_LDS).  Replica r has its own L[r], beta[r], J[r],
  * seed[r] and its own records; its spins, clusters and records are bit for
  * bit those of a plain sim created with the same parameters and swept the
- * same number of times.  All replicas share the sweep counter t.
- * Limits: 1 <= n <= 4095; every L[r] as for sw_create (the tile is 64 when
- * every L[r] is a multiple of 64, else 32); no labels or dense histogram. */
+ * same number of times, whatever its tile width and merge.  All replicas
+ * share the sweep counter t.  Limits: 1 <= n <= 4095; every L[r] as for
+ * sw_create; no labels or dense histogram. */
 typedef struct sw_batch sw_batch;
+
+#define SW_MERGE_AUTO 0   /* LDS merge when the replica has at most 16 tiles */
+#define SW_MERGE_LDS 1    /* the whole merge in one workgroup (<= 16 tiles)  */
+#define SW_MERGE_GLOBAL 2 /* the global merge                                */
 
 /* Device bytes of a batch with these lattice sides, `ring` records per
  * replica (0 = 1024) and tile side (0 = automatic, 32, 64); 0 when the
@@ -273,9 +281,8 @@ size_t sw_batch_workspace_bytes(int32_t n, const int32_t *L, int64_t ring, int32
 /* Creates a batch of n replicas, L/beta/J/seed being arrays of length n
  * (host memory, read during the call), all started with `init`
  * (SW_INIT_HOT / SW_INIT_COLD), t = 0.  tile: the side of the tiles every
- * replica is labelled in -- 0 (64 when every L is a multiple of 64, else
- * 32), 32 or 64 (results do not depend on it; the binding's autotuner picks
- * the faster one for a given replica table).  dev_workspace: NULL (the library
+ * replica is labelled in -- 0 (each replica: 64 when its L is a multiple of
+ * 64, else 32), 32 or 64 (results do not depend on it); merge automatic.  dev_workspace: NULL (the library
  * allocates) or a 256-byte-aligned device buffer of >= ws_bytes =
  * sw_batch_workspace_bytes(...) bytes that the caller keeps alive until
  * sw_batch_destroy.  hip_stream: the stream for all of the batch's work
@@ -287,15 +294,29 @@ int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const doubl
 
 /* Batches of q-state Potts replicas (the model of sw_config.q): as
  * sw_batch_workspace_bytes / sw_batch_create, with q[0..n-1] the q (2..8)
- * of every replica.  tile 0 selects 64-wide tiles when every L is a
- * multiple of 64 and every q is at most 4, else 32-wide; tile 64 with a q
- * above 4 is SW_EINVAL.  Every replica's bits are those of a plain Potts
+ * of every replica.  tile 0 selects, per replica, 64-wide tiles when its L
+ * is a multiple of 64 and its q is at most 4, else 32-wide; tile 64 with a
+ * q above 4 is SW_EINVAL.  Every replica's bits are those of a plain Potts
  * sim with the same parameters. */
 size_t sw_batch_workspace_bytes_potts(int32_t n, const int32_t *L, const int32_t *q, int64_t ring,
                                       int32_t tile);
 int sw_batch_create_potts(int32_t n, const int32_t *L, const double *beta, const double *J,
                           const uint64_t *seed, const int32_t *q, int32_t init, int64_t ring, int32_t tile,
                           void *dev_workspace, size_t ws_bytes, void *hip_stream, sw_batch **out);
+
+/* General form: q (NULL: all Ising) gives every replica's model (0 Ising,
+ * 2..8 q-state Potts); tiles (NULL: automatic) every replica's tile width
+ * (0 automatic, 32, 64; as sw_config.tile); merge (NULL: automatic) every
+ * replica's merge (SW_MERGE_AUTO, SW_MERGE_LDS -- SW_EINVAL for a replica
+ * of more than 16 tiles -- or SW_MERGE_GLOBAL).  Replicas of different tile
+ * widths or models run in separate launch groups of the same sweep.  These
+ * choices change no result, only speed; the binding's autotuner picks them
+ * per lattice side. */
+size_t sw_batch_workspace_bytes_ex(int32_t n, const int32_t *L, const int32_t *q, const int32_t *tiles,
+                                   const int32_t *merge, int64_t ring);
+int sw_batch_create_ex(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
+                       const int32_t *q, const int32_t *tiles, const int32_t *merge, int32_t init, int64_t ring,
+                       void *dev_workspace, size_t ws_bytes, void *hip_stream, sw_batch **out);
 
 /* Re-initialises every replica (SW_INIT_HOT / SW_INIT_COLD) and sets t = 0. */
 int sw_batch_reset(sw_batch *batch, int32_t init_mode);
@@ -316,12 +337,15 @@ int sw_batch_series(sw_batch *batch, int32_t r, int64_t first, int64_t count, sw
 /* Current spins of replica r (n == L[r]^2), as sw_get_spins. */
 int sw_batch_get_spins(sw_batch *batch, int32_t r, int8_t *host, int64_t n);
 
-/* Number of replicas; index of the next sweep; side, bond threshold of
- * replica r (0 for a bad index); tile side used. */
+/* Number of replicas; index of the next sweep; side, bond threshold, tile
+ * width and merge (SW_MERGE_LDS / SW_MERGE_GLOBAL) of replica r (0 for a bad
+ * index); the tile width every replica uses (0 if they differ). */
 int32_t sw_batch_size(const sw_batch *batch);
 int64_t sw_batch_next_sweep(const sw_batch *batch);
 int32_t sw_batch_lattice(const sw_batch *batch, int32_t r);
 uint32_t sw_batch_threshold(const sw_batch *batch, int32_t r);
+int32_t sw_batch_replica_tile(const sw_batch *batch, int32_t r);
+int32_t sw_batch_replica_merge(const sw_batch *batch, int32_t r);
 int32_t sw_batch_tile(const sw_batch *batch);
 
 /* Destroys the batch (waits for its stream first); NULL is a no-op. */

@@ -125,6 +125,11 @@ _SIGNATURES = {
     "sw_batch_lattice": (ctypes.c_int32, [_P, ctypes.c_int32]),
     "sw_batch_threshold": (ctypes.c_uint32, [_P, ctypes.c_int32]),
     "sw_batch_tile": (ctypes.c_int32, [_P]),
+    "sw_batch_replica_tile": (ctypes.c_int32, [_P, ctypes.c_int32]),
+    "sw_batch_replica_merge": (ctypes.c_int32, [_P, ctypes.c_int32]),
+    "sw_batch_workspace_bytes_ex": (ctypes.c_size_t, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64]),
+    "sw_batch_create_ex": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int32,
+                                          ctypes.c_int64, _P, ctypes.c_size_t, _P, _P]),
     "sw_batch_destroy": (None, [_P]),
     "sw_server_job_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
     "sw_server_job_bytes_potts": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]),
@@ -323,22 +328,41 @@ def _replica_arrays(L, beta, J, seed):
     return n, La, ba, Ja, sa
 
 
-def sw_batch_workspace_bytes(L, ring: int = 0, tile: int = 0, q=None) -> int:
+SW_MERGE_AUTO, SW_MERGE_LDS, SW_MERGE_GLOBAL = 0, 1, 2
+
+
+def _per_replica(v, n):
+    return None if v is None else np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.int32), (n,)))
+
+
+def sw_batch_workspace_bytes(L, ring: int = 0, tile: int = 0, q=None, tiles=None, merge=None) -> int:
     La = np.ascontiguousarray(L, dtype=np.int32)
+    if tiles is not None or merge is not None:
+        qa, ta, ma = _per_replica(q, La.size), _per_replica(tiles, La.size), _per_replica(merge, La.size)
+        return int(lib().sw_batch_workspace_bytes_ex(La.size, _ptr(La), None if qa is None else _ptr(qa),
+                                                     None if ta is None else _ptr(ta),
+                                                     None if ma is None else _ptr(ma), ring))
     if q is not None:
-        qa = np.ascontiguousarray(np.broadcast_to(np.asarray(q, dtype=np.int32), (La.size,)))
+        qa = _per_replica(q, La.size)
         return int(lib().sw_batch_workspace_bytes_potts(La.size, _ptr(La), _ptr(qa), ring, tile))
     return int(lib().sw_batch_workspace_bytes(La.size, _ptr(La), ring, tile))
 
 
 def sw_batch_create(L, beta, J, seed, init: int = SW_INIT_HOT, ring: int = 0, tile: int = 0, ws_ptr: int = 0,
-                    ws_bytes: int = 0, stream_ptr: int = 0, q=None) -> int:
+                    ws_bytes: int = 0, stream_ptr: int = 0, q=None, tiles=None, merge=None) -> int:
     """q: None for Ising replicas (sw_batch_create), else the Potts q of every
-    replica (sw_batch_create_potts)."""
+    replica (sw_batch_create_potts); tiles / merge: per-replica tile widths
+    and merges (sw_batch_create_ex, where q may mix 0 = Ising and Potts)."""
     n, La, ba, Ja, sa = _replica_arrays(L, beta, J, seed)
     h = ctypes.c_void_p()
-    if q is not None:
-        qa = np.ascontiguousarray(np.broadcast_to(np.asarray(q, dtype=np.int32), (n,)))
+    if tiles is not None or merge is not None:
+        qa, ta, ma = _per_replica(q, n), _per_replica(tiles, n), _per_replica(merge, n)
+        _check(lib().sw_batch_create_ex(n, _ptr(La), _ptr(ba), _ptr(Ja), _ptr(sa),
+                                        None if qa is None else _ptr(qa), None if ta is None else _ptr(ta),
+                                        None if ma is None else _ptr(ma), init, ring, ws_ptr or None, ws_bytes,
+                                        stream_ptr or None, ctypes.byref(h)))
+    elif q is not None:
+        qa = _per_replica(q, n)
         _check(lib().sw_batch_create_potts(n, _ptr(La), _ptr(ba), _ptr(Ja), _ptr(sa), _ptr(qa), init, ring, tile,
                                            ws_ptr or None, ws_bytes, stream_ptr or None, ctypes.byref(h)))
     else:
@@ -482,9 +506,11 @@ class Batch:
     the same length."""
 
     def __init__(self, L, beta, J=1.0, seed=0, *, init: int = SW_INIT_HOT, ring: int = 0, tile: int = 0,
-                 q=None, device=None):
+                 q=None, tiles=None, merge=None, device=None):
         """q: None for Ising replicas, else the Potts q of every replica
-        (a scalar or a sequence)."""
+        (a scalar or a sequence; with tiles or merge given, 0 marks an Ising
+        replica); tiles / merge: per-replica tile widths (0, 32, 64) and
+        merges (SW_MERGE_*), scalars or sequences."""
         import torch
 
         if not torch.cuda.is_available():
@@ -492,15 +518,15 @@ class Batch:
         n, La, ba, Ja, sa = _replica_arrays(L, beta, J, seed)
         self.L = La.tolist()
         self.q = q
-        nbytes = sw_batch_workspace_bytes(La, ring, tile, q=q)
-        if nbytes == 0:
-            self.handle = sw_batch_create(La, ba, Ja, sa, init, ring, tile, q=q)  # raises with the reason
+        nbytes = sw_batch_workspace_bytes(La, ring, tile, q=q, tiles=tiles, merge=merge)
+        if nbytes == 0:  # raises with the reason
+            self.handle = sw_batch_create(La, ba, Ja, sa, init, ring, tile, q=q, tiles=tiles, merge=merge)
         dev = torch.device("cuda" if device is None else device)
         self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self._stream = torch.cuda.Stream(device=dev)
         torch.cuda.current_stream(dev).synchronize()
         self.handle = sw_batch_create(La, ba, Ja, sa, init, ring, tile, self._ws.data_ptr(), nbytes,
-                                      self._stream.cuda_stream, q=q)
+                                      self._stream.cuda_stream, q=q, tiles=tiles, merge=merge)
 
     def __len__(self) -> int:
         return len(self.L)
@@ -532,7 +558,14 @@ class Batch:
 
     @property
     def tile(self) -> int:
+        """The tile width every replica uses (0 if they differ)."""
         return int(lib().sw_batch_tile(self.handle))
+
+    def replica_tile(self, r: int) -> int:
+        return int(lib().sw_batch_replica_tile(self.handle, r))
+
+    def replica_merge(self, r: int) -> int:
+        return int(lib().sw_batch_replica_merge(self.handle, r))
 
     def close(self) -> None:
         h, self.handle = getattr(self, "handle", None), None

@@ -1,11 +1,13 @@
 """Autotuner for the tile side (32 or 64 sites) a lattice or a replica table
-is labelled in.
+is labelled in, and, per lattice side of a batch, for the merge schedule
+(the whole merge of a replica in one workgroup's LDS, or the global merge).
 
-The choice changes no result -- only speed: 64-wide tiles move less data
-across tile edges, 32-wide tiles give small lattices more workgroups.  The
-tuner times a few sweeps of every allowed choice on the current GPU, keeps
-the fastest, and caches the decision per device and workload in a JSON file
-(``$SWMI_TUNE_CACHE``, default ``~/.cache/paper_2302_14720_amd/tune.json``).
+The choices change no result -- only speed: 64-wide tiles move less data
+across tile edges, 32-wide tiles give small lattices more workgroups; the
+LDS merge saves a small replica four launches' worth of dependent steps.
+The tuner times a few sweeps of every allowed choice on the current GPU,
+keeps the fastest, and caches the decision per device and workload in a JSON
+file (``$SWMI_TUNE_CACHE``, default ``~/.cache/paper_2302_14720_amd/tune.json``).
 """
 from __future__ import annotations
 
@@ -16,7 +18,7 @@ import time
 
 import numpy as np
 
-from . import SW_INIT_HOT, Batch, Sim
+from . import SW_INIT_HOT, SW_MERGE_GLOBAL, SW_MERGE_LDS, Batch, Sim
 
 
 def cache_path() -> str:
@@ -96,3 +98,52 @@ def tune_sim(L: int, beta: float, J: float = 1.0, seed: int = 0, *, sweeps: int 
     best = min(ms, key=ms.get)
     _store(key, {"tile": best, "ms": {str(k): v for k, v in ms.items()}})
     return best, ms
+
+
+SMALL_TILES = 16  # replicas of at most this many tiles may take the LDS merge
+
+
+def _options(L: int, q: int):
+    tiles = [64, 32] if (L % 64 == 0 and q <= 4) else [32]
+    out = []
+    for t in tiles:
+        out.append((t, SW_MERGE_GLOBAL))
+        if (L // t) ** 2 <= SMALL_TILES:
+            out.append((t, SW_MERGE_LDS))
+    return out
+
+
+def tune_batch_per_side(L, beta, J=1.0, seed=0, q=None, *, sweeps: int = 10, warmup: int = 3,
+                        use_cache: bool = True):
+    """Tile side and merge for every replica of a table, chosen per lattice
+    side (and Potts q): the replicas of each side are timed as a batch of
+    their own under every allowed (tile, merge) pair and the fastest pair is
+    kept.  Returns (tiles, merges, {(L, q): {(tile, merge): ms per sweep}})."""
+    La = np.asarray(L, dtype=np.int32)
+    n = La.size
+    ba = np.broadcast_to(np.asarray(beta, dtype=np.float64), (n,))
+    Ja = np.broadcast_to(np.asarray(J, dtype=np.float64), (n,))
+    sa = np.broadcast_to(np.asarray(seed, dtype=np.uint64), (n,))
+    qa = np.zeros(n, dtype=np.int32) if q is None else np.broadcast_to(np.asarray(q, dtype=np.int32), (n,))
+    tiles = np.zeros(n, dtype=np.int32)
+    merges = np.zeros(n, dtype=np.int32)
+    table = {}
+    for side, qq in sorted({(int(a), int(b)) for a, b in zip(La, qa)}):
+        idx = np.nonzero((La == side) & (qa == qq))[0]
+        key = f"{_device()}|batch-side|L={side}|q={qq}|n={idx.size}"
+        opts = _options(side, qq)
+        hit = _load().get(key) if use_cache else None
+        if hit and tuple(hit["best"]) in opts:
+            best = tuple(hit["best"])
+            ms = {tuple(int(x) for x in k.split(",")): v for k, v in hit["ms"].items()}
+        else:
+            ms = {}
+            for t, m in opts:
+                ms[(t, m)] = _time(lambda t=t, m=m: Batch(La[idx], ba[idx], Ja[idx], sa[idx], init=SW_INIT_HOT,
+                                                          ring=64, q=qa[idx], tiles=t, merge=m),
+                                   warmup, sweeps)
+            best = min(ms, key=ms.get)
+            _store(key, {"best": list(best), "ms": {f"{k[0]},{k[1]}": v for k, v in ms.items()}})
+        tiles[idx], merges[idx] = best
+        table[(side, qq)] = ms
+    return tiles, merges, table

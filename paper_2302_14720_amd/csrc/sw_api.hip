@@ -584,10 +584,15 @@ void sw_destroy(sw_sim *s) {
 
 // ===================================================================== batches
 
+// Launch groups of a batch: Ising and Potts replicas, each with 64-wide or
+// 32-wide tiles, run different instantiations of the tile kernels.
+constexpr int kBatchGroups = 4;
+
 struct sw_batch {
     std::vector<sw_config> cfg;
-    std::vector<Dev> dev;  // host copies of the replicas' device views
-    swmi::BatchDev bd;
+    std::vector<Dev> dev;      // host copies of the replicas' device views
+    std::vector<uint8_t> lds;  // 1 where the replica's merge runs in LDS
+    swmi::BatchDev bd[kBatchGroups];
     hipStream_t stream;
     bool own_stream;
     void *ws;
@@ -605,69 +610,70 @@ namespace {
 
 constexpr int64_t kDefaultBatchRing = 1024;
 
+int batch_group(const Dev &d) { return (d.q ? 2 : 0) + (d.tw == 64 ? 0 : 1); }
+
 struct BatchPlan {
-    bool potts;
     std::vector<sw_config> cfg;
-    std::vector<size_t> base;  // workspace offset of every replica
-    size_t devs, tmap, wmap, gmap, umap, rmap, total;
-    uint32_t ntiles, nwmap, ngroups, nugroups, tw;
+    std::vector<size_t> base;   // workspace offset of every replica
+    std::vector<uint8_t> lds;   // merge in LDS
+    size_t devs, maps, total;
+    size_t map_words;
 };
 
 // Validates the replica table and lays out the batch workspace: the
 // replicas' buffers one after another, then the Dev table and the maps.
-// q: NULL for Ising replicas, else the Potts q (2..8) of every replica.
+// q: NULL for Ising replicas, else the Potts q of every replica (0: Ising,
+// 2..8: Potts).  tiles: NULL (every replica takes `tile`), else the tile
+// width of every replica (0 automatic, 32, 64).  merge: NULL (automatic),
+// else per replica SW_MERGE_AUTO / SW_MERGE_LDS / SW_MERGE_GLOBAL.
 int plan_batch(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
-               const int32_t *q, int32_t init, int64_t ring, int32_t tile, BatchPlan *p) {
+               const int32_t *q, const int32_t *tiles, const int32_t *merge, int32_t init, int64_t ring,
+               int32_t tile, BatchPlan *p) {
     if (n < 1 || n > swmi::kMaxReplicas)
         return fail(SW_EINVAL, "the number of replicas must be in [1, " + std::to_string(swmi::kMaxReplicas) + "]");
     if (!L || !beta || !J || !seed) return fail(SW_EINVAL, "replica arrays must not be NULL");
     if (init != SW_INIT_HOT && init != SW_INIT_COLD) return fail(SW_EINVAL, "init must be SW_INIT_HOT or SW_INIT_COLD");
     if (tile != 0 && tile != 32 && tile != 64) return fail(SW_EINVAL, "tile must be 0, 32 or 64");
-    bool all64 = true, small_q = true;
-    for (int32_t r = 0; r < n; ++r) {
-        all64 = all64 && (L[r] % 64 == 0);
-        if (q && (q[r] < 2 || q[r] > swmi::kMaxQ))
-            return fail(SW_EINVAL, "replica " + std::to_string(r) + ": Potts q must be in [2, 8]");
-        small_q = small_q && (!q || q[r] <= 4);
-    }
-    if (tile == 64 && !all64) return fail(SW_EINVAL, "tile 64 needs every L to be a multiple of 64");
-    if (tile == 64 && !small_q) return fail(SW_EINVAL, "tile 64 needs every Potts q to be at most 4");
-    p->potts = q != nullptr;
-    p->tw = tile != 0 ? (uint32_t)tile : (all64 && small_q) ? 64u : 32u;
     p->cfg.assign((size_t)n, sw_config{});
     p->base.assign((size_t)n, 0);
+    p->lds.assign((size_t)n, 0);
     size_t off = 0;
-    p->ntiles = p->ngroups = p->nugroups = 0;
+    swmi::BatchMaps m[kBatchGroups];
     for (int32_t r = 0; r < n; ++r) {
+        const std::string who = "replica " + std::to_string(r) + ": ";
         sw_config &c = p->cfg[(size_t)r];
         sw_config_init(&c, L[r], beta[r], J[r], seed[r]);
         c.q = q ? q[r] : 0;
+        if (c.q != 0 && (c.q < 2 || c.q > swmi::kMaxQ)) return fail(SW_EINVAL, who + "Potts q must be 0 or in [2, 8]");
         c.init = init;
-        c.tile = (int32_t)p->tw;
+        c.tile = tiles ? tiles[r] : tile;
+        if (c.tile != 0 && c.tile != 32 && c.tile != 64) return fail(SW_EINVAL, who + "tile must be 0, 32 or 64");
         c.ring = ring > 0 ? ring : kDefaultBatchRing;
         const int rc = validate(&c);
-        if (rc != SW_OK) return fail(rc, "replica " + std::to_string(r) + ": " + swmi::last_error());
+        if (rc != SW_OK) return fail(rc, who + swmi::last_error());
+        c.tile = resolve_tile(c);
+        const int32_t mg = merge ? merge[r] : SW_MERGE_AUTO;
+        if (mg != SW_MERGE_AUTO && mg != SW_MERGE_LDS && mg != SW_MERGE_GLOBAL)
+            return fail(SW_EINVAL, who + "merge must be SW_MERGE_AUTO, SW_MERGE_LDS or SW_MERGE_GLOBAL");
+        const uint32_t nt = (uint32_t)((c.L / c.tile) * (c.L / c.tile));
+        if (mg == SW_MERGE_LDS && nt > swmi::kSmallTiles)
+            return fail(SW_EINVAL, who + "the LDS merge takes at most " + std::to_string(swmi::kSmallTiles) + " tiles");
+        p->lds[(size_t)r] = (mg != SW_MERGE_GLOBAL && nt <= swmi::kSmallTiles) ? 1u : 0u;
         const Layout lo = layout_of(c);
         p->base[(size_t)r] = off;
         off = align_up(off + lo.total);
-        const uint32_t nt = (uint32_t)((c.L / p->tw) * (c.L / p->tw));
-        p->ntiles += nt;
-        p->ngroups += (nt + swmi::kGroupTiles - 1) / swmi::kGroupTiles;
-        const uint32_t ngx = ((uint32_t)c.L / p->tw + swmi::kUG - 1u) / swmi::kUG;
-        p->nugroups += ngx * ngx;
+        const Dev d = make_dev(c, nullptr, lo);
+        m[batch_group(d)].add((uint32_t)r, d, p->lds[(size_t)r] != 0);
     }
-    p->nwmap = (p->ntiles + 3u) & ~3u;
+    p->map_words = 0;
+    for (const swmi::BatchMaps &g : m) p->map_words += g.words();
     auto take = [&](size_t bytes) {
         const size_t at = off;
         off = align_up(off + bytes);
         return at;
     };
     p->devs = take((size_t)n * sizeof(Dev));
-    p->tmap = take((size_t)p->ntiles * 4);
-    p->wmap = take((size_t)p->nwmap * 4);
-    p->gmap = take((size_t)p->ngroups * 4);
-    p->umap = take((size_t)p->nugroups * 4);
-    p->rmap = take((size_t)n * 4);
+    p->maps = take(p->map_words * 4);
     p->total = off;
     return SW_OK;
 }
@@ -687,8 +693,16 @@ void batch_drop_graph(sw_batch *b) {
     b->graph_tried = false;
 }
 
-// One batched sweep captured as a graph (five kernel nodes); on any capture
-// failure the kernels are launched directly.
+hipError_t batch_launch_sweep(const sw_batch *b) {
+    for (int g = 0; g < kBatchGroups; ++g) {
+        const hipError_t e = swmi::launch_batch_sweep(b->bd[g], b->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// One batched sweep captured as a graph; on any capture failure the kernels
+// are launched directly.
 void batch_ensure_graph(sw_batch *b) {
     if (b->graph_tried) return;
     b->graph_tried = true;
@@ -697,7 +711,7 @@ void batch_ensure_graph(sw_batch *b) {
         (void)hipGetLastError();
         return;
     }
-    const hipError_t le = swmi::launch_batch_sweep(b->bd, b->stream);
+    const hipError_t le = batch_launch_sweep(b);
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(b->stream, &g);
     if (le != hipSuccess || ce != hipSuccess || g == nullptr) {
@@ -721,22 +735,24 @@ int batch_check_replica(const sw_batch *b, int32_t r) {
     return SW_OK;
 }
 
-size_t batch_bytes(int32_t n, const int32_t *L, const int32_t *q, int64_t ring, int32_t tile) {
+size_t batch_bytes(int32_t n, const int32_t *L, const int32_t *q, const int32_t *tiles, const int32_t *merge,
+                   int64_t ring, int32_t tile) {
     if (n < 1 || n > swmi::kMaxReplicas || !L) return 0;
     std::vector<double> beta((size_t)n, 0.0), J((size_t)n, 1.0);
     std::vector<uint64_t> seed((size_t)n, 0u);
     BatchPlan p;
-    if (plan_batch(n, L, beta.data(), J.data(), seed.data(), q, SW_INIT_HOT, ring, tile, &p) != SW_OK) return 0;
+    if (plan_batch(n, L, beta.data(), J.data(), seed.data(), q, tiles, merge, SW_INIT_HOT, ring, tile, &p) != SW_OK)
+        return 0;
     return p.total;
 }
 
 int batch_create(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
-                 const int32_t *q, int32_t init, int64_t ring, int32_t tile, void *dev_workspace, size_t ws_bytes,
-                 void *hip_stream, sw_batch **out) {
+                 const int32_t *q, const int32_t *tiles, const int32_t *merge, int32_t init, int64_t ring,
+                 int32_t tile, void *dev_workspace, size_t ws_bytes, void *hip_stream, sw_batch **out) {
     if (!out) return fail(SW_EINVAL, "out is NULL");
     *out = nullptr;
     BatchPlan p;
-    int rc = plan_batch(n, L, beta, J, seed, q, init, ring, tile, &p);
+    int rc = plan_batch(n, L, beta, J, seed, q, tiles, merge, init, ring, tile, &p);
     if (rc != SW_OK) return rc;
     if (dev_workspace && ws_bytes < p.total)
         return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes");
@@ -779,49 +795,31 @@ int batch_create(int32_t n, const int32_t *L, const double *beta, const double *
     }
     char *base = (char *)b->ws;
     b->cfg = p.cfg;
+    b->lds = p.lds;
     b->dev.resize(p.cfg.size());
-    std::vector<uint32_t> tmap, wmap, gmap, umap, rmap;
-    tmap.reserve(p.ntiles);
-    gmap.reserve(p.ngroups);
+    swmi::BatchMaps m[kBatchGroups];
     for (size_t r = 0; r < p.cfg.size(); ++r) {
         b->dev[r] = make_dev(p.cfg[r], base + p.base[r], layout_of(p.cfg[r]));
-        rmap.push_back((uint32_t)r);
-        const uint32_t tag = (uint32_t)r << swmi::kMapShift;
-        for (uint32_t t = 0; t < b->dev[r].ntiles; ++t) tmap.push_back(tag | t);
-        for (uint32_t g = 0; g < b->dev[r].ngroups; ++g) gmap.push_back(tag | g);
-        const uint32_t ngx = (b->dev[r].ntx + swmi::kUG - 1u) / swmi::kUG;
-        for (uint32_t g = 0; g < ngx * ngx; ++g) umap.push_back(tag | g);
+        m[batch_group(b->dev[r])].add((uint32_t)r, b->dev[r], p.lds[r] != 0);
     }
-    wmap = tmap;
-    wmap.resize(p.nwmap, swmi::kMapNone);
-    b->bd.devs = (const Dev *)(base + p.devs);
-    b->bd.tmap = (const uint32_t *)(base + p.tmap);
-    b->bd.wmap = (const uint32_t *)(base + p.wmap);
-    b->bd.gmap = (const uint32_t *)(base + p.gmap);
-    b->bd.umap = (const uint32_t *)(base + p.umap);
-    b->bd.rmap = (const uint32_t *)(base + p.rmap);
-    b->bd.nugroups = p.nugroups;
-    b->bd.n = (uint32_t)p.cfg.size();
-    b->bd.ntiles = p.ntiles;
-    b->bd.nwmap = p.nwmap;
-    b->bd.ngroups = p.ngroups;
-    b->bd.tw = p.tw;
-    b->bd.potts = p.potts ? 1u : 0u;
+    std::vector<uint32_t> host;
+    host.reserve(p.map_words);
+    const uint32_t *dmaps = (const uint32_t *)(base + p.maps);
+    for (int g = 0; g < kBatchGroups; ++g) {
+        swmi::BatchDev &bd = b->bd[g];
+        bd = swmi::BatchDev{};
+        bd.devs = (const Dev *)(base + p.devs);
+        bd.tw = (g & 1) ? 32u : 64u;
+        bd.potts = g >= 2 ? 1u : 0u;
+        m[g].emit(host, dmaps, bd);
+    }
 
     e = hipMemsetAsync(b->ws, 0, p.total, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(base + p.devs, b->dev.data(), b->dev.size() * sizeof(Dev), hipMemcpyHostToDevice,
                            b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(base + p.tmap, tmap.data(), tmap.size() * 4, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(base + p.wmap, wmap.data(), wmap.size() * 4, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(base + p.gmap, gmap.data(), gmap.size() * 4, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(base + p.umap, umap.data(), umap.size() * 4, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(base + p.rmap, rmap.data(), rmap.size() * 4, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !host.empty())
+        e = hipMemcpyAsync(base + p.maps, host.data(), host.size() * 4, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         rc = hip_fail(e, "setting up the batch workspace");
@@ -843,18 +841,24 @@ int batch_create(int32_t n, const int32_t *L, const double *beta, const double *
 extern "C" {
 
 size_t sw_batch_workspace_bytes(int32_t n, const int32_t *L, int64_t ring, int32_t tile) {
-    return batch_bytes(n, L, nullptr, ring, tile);
+    return batch_bytes(n, L, nullptr, nullptr, nullptr, ring, tile);
 }
 
 size_t sw_batch_workspace_bytes_potts(int32_t n, const int32_t *L, const int32_t *q, int64_t ring, int32_t tile) {
     if (!q) return 0;
-    return batch_bytes(n, L, q, ring, tile);
+    return batch_bytes(n, L, q, nullptr, nullptr, ring, tile);
+}
+
+size_t sw_batch_workspace_bytes_ex(int32_t n, const int32_t *L, const int32_t *q, const int32_t *tiles,
+                                   const int32_t *merge, int64_t ring) {
+    return batch_bytes(n, L, q, tiles, merge, ring, 0);
 }
 
 int sw_batch_create(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
                     int32_t init, int64_t ring, int32_t tile, void *dev_workspace, size_t ws_bytes,
                     void *hip_stream, sw_batch **out) {
-    return batch_create(n, L, beta, J, seed, nullptr, init, ring, tile, dev_workspace, ws_bytes, hip_stream, out);
+    return batch_create(n, L, beta, J, seed, nullptr, nullptr, nullptr, init, ring, tile, dev_workspace, ws_bytes,
+                        hip_stream, out);
 }
 
 int sw_batch_create_potts(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
@@ -864,7 +868,20 @@ int sw_batch_create_potts(int32_t n, const int32_t *L, const double *beta, const
         if (out) *out = nullptr;
         return fail(SW_EINVAL, "q must not be NULL");
     }
-    return batch_create(n, L, beta, J, seed, q, init, ring, tile, dev_workspace, ws_bytes, hip_stream, out);
+    for (int32_t r = 0; n > 0 && r < n; ++r)
+        if (q[r] < 2 || q[r] > swmi::kMaxQ) {
+            if (out) *out = nullptr;
+            return fail(SW_EINVAL, "replica " + std::to_string(r) + ": Potts q must be in [2, 8]");
+        }
+    return batch_create(n, L, beta, J, seed, q, nullptr, nullptr, init, ring, tile, dev_workspace, ws_bytes,
+                        hip_stream, out);
+}
+
+int sw_batch_create_ex(int32_t n, const int32_t *L, const double *beta, const double *J, const uint64_t *seed,
+                       const int32_t *q, const int32_t *tiles, const int32_t *merge, int32_t init, int64_t ring,
+                       void *dev_workspace, size_t ws_bytes, void *hip_stream, sw_batch **out) {
+    return batch_create(n, L, beta, J, seed, q, tiles, merge, init, ring, 0, dev_workspace, ws_bytes, hip_stream,
+                        out);
 }
 
 int sw_batch_reset(sw_batch *b, int32_t init_mode) {
@@ -896,9 +913,9 @@ int sw_batch_sweep(sw_batch *b, int64_t n) {
         if (b->gexec)
             HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
         else
-            HIP_TRY(swmi::launch_batch_sweep(b->bd, b->stream));
+            HIP_TRY(batch_launch_sweep(b));
     }
-    HIP_TRY(swmi::launch_batch_resolve(b->bd, b->stream));
+    for (int g = 0; g < kBatchGroups; ++g) HIP_TRY(swmi::launch_batch_resolve(b->bd[g], b->stream));
     b->next_sweep += (uint64_t)n;
     return SW_OK;
 }
@@ -972,7 +989,20 @@ int32_t sw_batch_lattice(const sw_batch *b, int32_t r) {
 uint32_t sw_batch_threshold(const sw_batch *b, int32_t r) {
     return (b && r >= 0 && (size_t)r < b->dev.size()) ? b->dev[(size_t)r].T : 0u;
 }
-int32_t sw_batch_tile(const sw_batch *b) { return b ? (int32_t)b->bd.tw : 0; }
+int32_t sw_batch_tile(const sw_batch *b) {
+    if (!b || b->dev.empty()) return 0;
+    const uint32_t tw = b->dev[0].tw;
+    for (const Dev &d : b->dev)
+        if (d.tw != tw) return 0;
+    return (int32_t)tw;
+}
+int32_t sw_batch_replica_tile(const sw_batch *b, int32_t r) {
+    return (b && r >= 0 && (size_t)r < b->dev.size()) ? (int32_t)b->dev[(size_t)r].tw : 0;
+}
+int32_t sw_batch_replica_merge(const sw_batch *b, int32_t r) {
+    if (!b || r < 0 || (size_t)r >= b->dev.size()) return 0;
+    return b->lds[(size_t)r] ? SW_MERGE_LDS : SW_MERGE_GLOBAL;
+}
 
 void sw_batch_destroy(sw_batch *b) {
     if (!b) return;

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <string>
+#include <vector>
 
 #include "sw_internal.h"
 
@@ -32,6 +33,58 @@ int resolve_tile(const sw_config &c);
 int validate(const sw_config *c);
 Layout layout_of(const sw_config &c);
 Dev make_dev(const sw_config &c, char *base, const Layout &lo);
+
+// Host-side work maps of one launch group of a batch (one tile width, Ising
+// or Potts): add() files the replica in slot `slot` of the Dev table under
+// the global merge, or under the LDS merge (k_smerge_b) when `small` is set
+// and it has at most kSmallTiles tiles; emit() appends the maps to `host`
+// (which will be copied to dev_base) and points the BatchDev at them.
+struct BatchMaps {
+    std::vector<uint32_t> t, w, g, u, r, s, a;
+    void add(uint32_t slot, const Dev &d, bool small) {
+        const uint32_t tag = slot << kMapShift;
+        a.push_back(slot);
+        for (uint32_t i = 0; i < d.ntiles; ++i) t.push_back(tag | i);
+        if (small && d.ntiles <= kSmallTiles) {
+            s.push_back(slot);
+            return;
+        }
+        r.push_back(slot);
+        for (uint32_t i = 0; i < d.ntiles; ++i) w.push_back(tag | i);
+        for (uint32_t i = 0; i < d.ngroups; ++i) g.push_back(tag | i);
+        const uint32_t ngx = (d.ntx + kUG - 1u) / kUG;
+        for (uint32_t i = 0; i < ngx * ngx; ++i) u.push_back(tag | i);
+    }
+    size_t words() const {
+        return t.size() + ((w.size() + 3u) & ~size_t(3)) + g.size() + u.size() + r.size() + s.size() + a.size();
+    }
+    void emit(std::vector<uint32_t> &host, const uint32_t *dev_base, BatchDev &b) const {
+        const size_t at = host.size();
+        b.ntiles = (uint32_t)t.size();
+        b.nwmap = (uint32_t)((w.size() + 3u) & ~size_t(3));
+        b.ngroups = (uint32_t)g.size();
+        b.nugroups = (uint32_t)u.size();
+        b.n = (uint32_t)r.size();
+        b.nsmall = (uint32_t)s.size();
+        b.nall = (uint32_t)a.size();
+        host.insert(host.end(), t.begin(), t.end());
+        host.insert(host.end(), w.begin(), w.end());
+        host.resize(at + b.ntiles + b.nwmap, kMapNone);
+        host.insert(host.end(), g.begin(), g.end());
+        host.insert(host.end(), u.begin(), u.end());
+        host.insert(host.end(), r.begin(), r.end());
+        host.insert(host.end(), s.begin(), s.end());
+        host.insert(host.end(), a.begin(), a.end());
+        const uint32_t *p = dev_base + at;
+        b.tmap = p;
+        b.wmap = p + b.ntiles;
+        b.gmap = b.wmap + b.nwmap;
+        b.umap = b.gmap + b.ngroups;
+        b.rmap = b.umap + b.nugroups;
+        b.smap = b.rmap + b.n;
+        b.amap = b.smap + b.nsmall;
+    }
+};
 
 }  // namespace swmi
 

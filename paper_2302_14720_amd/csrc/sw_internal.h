@@ -102,16 +102,24 @@ constexpr uint32_t kMapNone = 0xFFFFFFFFu;
 constexpr int32_t kMaxReplicas = 4095;
 static_assert(((uint32_t)(kMaxReplicas - 1) << kMapShift | kMapMask) != kMapNone, "map entry collides with kMapNone");
 
+// Replicas of at most kSmallTiles tiles may run their whole merge in one
+// workgroup, in LDS (k_smerge_b); the others run the global merge.
+constexpr uint32_t kSmallTiles = 16;
+
 struct BatchDev {
-    const Dev *devs;       // [n] the replicas' Dev, in device memory
-    const uint32_t *tmap;  // [ntiles] one entry per tile (k_tile, k_resolve)
+    const Dev *devs;       // the replicas' Dev, in device memory
+    const uint32_t *tmap;  // [ntiles] one entry per tile of every replica (k_tile, k_resolve)
     const uint32_t *wmap;  // [nwmap] one per wavefront of k_union, kMapNone-padded to 4
     const uint32_t *gmap;  // [ngroups] one per group of kGroupTiles tiles (k_flatten, k_roots)
     const uint32_t *umap;  // [nugroups] one per kUG x kUG group of tiles (k_ulocal)
-    const uint32_t *rmap;  // [n] the replicas (indices into devs) this launch covers
+    const uint32_t *rmap;  // [n] the replicas (indices into devs) of the global merge
+    const uint32_t *smap;  // [nsmall] the replicas merged in LDS
+    const uint32_t *amap;  // [nall] every replica of the launch (records after k_resolve)
     uint32_t n, ntiles, nwmap, ngroups, nugroups, tw;
+    uint32_t nsmall, nall;
     uint32_t potts;        // 1: every replica is a Potts model (q in its Dev)
 };
+
 
 // Paths with labels in global memory: stages 0..4 of a sweep (bonds and, for
 // cubic bricks, brick-local clusters; global labelling by iterated label

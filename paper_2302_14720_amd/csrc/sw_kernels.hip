@@ -47,9 +47,10 @@ __device__ __forceinline__ typename RowOf<TW>::T row_gather(uint32_t piece) {
 
 // Workgroup b runs on XCD b % 8; give each XCD a contiguous band of tiles so
 // that neighbouring tiles (which share halo rows and cache lines) meet in
-// the same L2.
+// the same L2 (the last n mod 8 blocks keep their own index).
 __device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t n) {
-    if ((n & 7u) == 0u) return (b & 7u) * (n >> 3) + (b >> 3);
+    const uint32_t n8 = n & ~7u;
+    if (b < n8) return (b & 7u) * (n8 >> 3) + (b >> 3);
     return b;
 }
 
@@ -764,7 +765,7 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
 // those of its own plain sweep.
 template <int TW, bool POTTS = false>
 __global__ __launch_bounds__(TW *TW / 16) void k_tile_b(const Dev *devs, const uint32_t *map) {
-    const uint32_t e = map[blockIdx.x];
+    const uint32_t e = map[tile_of_block(blockIdx.x, gridDim.x)];
     tile_body<TW, POTTS>(devs[e >> kMapShift], e & kMapMask);
 }
 
@@ -1283,6 +1284,140 @@ __global__ __launch_bounds__(256) void k_record_b(const Dev *devs, const uint32_
 }
 
 // =====================================================================
+// k_smerge_b: the whole cross-tile part of a sweep of one small replica
+// (at most kSmallTiles tiles) in one workgroup, in LDS: unions across every
+// tile edge (Sec. 2.3), every node to its root with the cluster's size and
+// smallest site, the new spin of every node's cluster (Sec. 2.4), the
+// cluster statistics and the record (Sec. 2.5) -- the work of k_ulocal,
+// k_union, k_flatten, k_roots and k_record for that replica, same results.
+// Nodes are numbered locally in global-index order (tile by tile), so the
+// root of a set is its node with the smallest global index, as in the
+// global merge.
+// =====================================================================
+constexpr uint32_t kSmallNodes = kSmallTiles * 252u;
+
+__device__ __forceinline__ void smerge_body(const Dev &d) {
+    __shared__ uint32_t s_par[kSmallNodes];
+    __shared__ uint32_t s_key[kSmallNodes];
+    __shared__ uint32_t s_sz[kSmallNodes];
+    __shared__ uint32_t s_off[kSmallTiles + 1];
+    __shared__ unsigned long long s_acc[GP_END];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint64_t tsw = *d.tdev;
+    const uint32_t t = (uint32_t)tsw, pc = (uint32_t)(tsw & 1u);
+    const uint32_t nt = d.ntiles, tw = d.tw, ntx = d.ntx;
+    uint32_t *par = d.parent[pc];
+    if (tid == 0u) {
+        uint32_t o = 0u;
+        for (uint32_t T = 0; T < nt; ++T) {
+            s_off[T] = o;
+            o += min(d.nk[pc][T], tw == 64u ? 252u : 124u);
+        }
+        s_off[nt] = o;
+    }
+    if (tid < (uint32_t)GP_END) s_acc[tid] = 0ull;
+    __syncthreads();
+    const uint32_t n = s_off[nt];
+    // local node i: tile T (s_off[T] <= i < s_off[T + 1]), slot i - s_off[T]
+    auto tile_of = [&](uint32_t i) {
+        uint32_t T = 0u;
+        while (T + 1u < nt && s_off[T + 1u] <= i) ++T;
+        return T;
+    };
+    for (uint32_t i = tid; i < n; i += 256u) {
+        const uint32_t T = tile_of(i), node = T * kNodeSlots + (i - s_off[T]);
+        s_par[i] = i;
+        s_key[i] = d.key[node];
+        s_sz[i] = d.nsize[node];
+    }
+    __syncthreads();
+    // bonds across every tile edge, E and N, periodic; a run of bonds along
+    // an edge between the same two nodes needs one union
+    for (uint32_t f0 = 0; f0 < nt * 2u * tw; f0 += 256u) {
+        const uint32_t f = f0 + tid;
+        const bool in = f < nt * 2u * tw;
+        const uint32_t T = in ? f / (2u * tw) : 0u, dir = (f / tw) & 1u, i = f % tw;
+        const uint32_t tx = T % ntx, ty = T / ntx;
+        const uint32_t nb = dir == 0u ? ty * ntx + (tx + 1u == ntx ? 0u : tx + 1u)
+                                      : (ty + 1u == ntx ? 0u : ty + 1u) * ntx + tx;
+        const uint8_t *ea = d.edge + (size_t)T * 4u * tw, *eb = d.edge + (size_t)nb * 4u * tw;
+        const bool has = in && ((d.xb[2u * T + dir] >> i) & 1u);
+        const uint32_t a = s_off[T] + (dir == 0u ? ea[1u * tw + i] : ea[3u * tw + i]);
+        const uint32_t b = s_off[nb] + (dir == 0u ? eb[0u * tw + i] : eb[2u * tw + i]);
+        const uint32_t pa = __shfl_up(a, 1, 64), pb = __shfl_up(b, 1, 64);
+        const int ph = __shfl_up((int)has, 1, 64);
+        const bool dup = i > 0u && lane > 0u && ph && pa == a && pb == b;
+        if (has && !dup) lds_union(s_par, a, b);
+    }
+    __syncthreads();
+    // every node to its root; sizes and smallest sites into the roots
+    for (uint32_t i = tid; i < n; i += 256u) {
+        const uint32_t r = lds_root(s_par, i);
+        if (r != i) {
+            atomicMin(&s_key[r], s_key[i]);
+            atomicAdd(&s_sz[r], s_sz[i]);
+            const uint32_t T = tile_of(i), Tr = tile_of(r);
+            par[T * kNodeSlots + (i - s_off[T])] = Tr * kNodeSlots + (r - s_off[Tr]);
+        }
+    }
+    __syncthreads();
+    // the new spin of every node's cluster, drawn from its smallest site;
+    // statistics of the cross-tile clusters
+    uint64_t cn = 0, cmx = 0, csq = 0;
+    for (uint32_t i = tid; i < n; i += 256u) {
+        const uint32_t r = lds_root(s_par, i), T = tile_of(i);
+        const uint32_t rkey = s_key[r];
+        d.rspin[T * kNodeSlots + (i - s_off[T])] =
+            d.q ? potts_spin(rkey, t, d.q, d.seed_lo, d.seed_hi) : cluster_spin(rkey, t, d.seed_lo, d.seed_hi);
+        if (r == i) {
+            const uint32_t S = s_sz[i];
+            ++cn;
+            cmx = max(cmx, (uint64_t)S);
+            csq += (uint64_t)S * S;
+            atomicAdd(&s_acc[GP_HIST + 31 - __clz((int)max(S, 1u))], 1ull);
+            if (d.dense) atomicAdd(reinterpret_cast<unsigned long long *>(&d.dense[S]), 1ull);
+        }
+    }
+    // the tile partials (interior clusters, energy and magnetisation of the
+    // incoming configuration, Potts populations)
+    int64_t ce = 0, cm = 0;
+    for (uint32_t T = tid; T < nt; T += 256u) {
+        const int32_t *tp = d.tpart + (size_t)T * kTilePart;
+        ce += tp[TP_E];
+        cm += tp[TP_M];
+        cn += (uint32_t)tp[TP_N];
+        cmx = max(cmx, (uint64_t)(uint32_t)tp[TP_MAX]);
+        csq += (uint32_t)tp[TP_SQ];
+        for (int b = 0; b < 12; ++b)
+            if (tp[TP_HIST + b]) atomicAdd(&s_acc[GP_HIST + b], (unsigned long long)(uint32_t)tp[TP_HIST + b]);
+        if (d.q)
+            for (int k = 0; k < kMaxQ; ++k)
+                if (tp[TP_CNT + k]) atomicAdd(&s_acc[GP_CNT + k], (unsigned long long)(uint32_t)tp[TP_CNT + k]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        cn += __shfl_xor(cn, o, 64);
+        cmx = max(cmx, (uint64_t)__shfl_xor((unsigned long long)cmx, o, 64));
+        csq += __shfl_xor(csq, o, 64);
+        ce += __shfl_xor(ce, o, 64);
+        cm += __shfl_xor(cm, o, 64);
+    }
+    if (lane == 0u) {
+        atomicAdd(&s_acc[GP_N], (unsigned long long)cn);
+        atomicMax(&s_acc[GP_MAX], (unsigned long long)cmx);
+        atomicAdd(&s_acc[GP_SQ], (unsigned long long)csq);
+        atomicAdd(&s_acc[GP_E], (unsigned long long)ce);
+        atomicAdd(&s_acc[GP_M], (unsigned long long)cm);
+    }
+    __syncthreads();
+    record_write(d, reinterpret_cast<const uint64_t *>(s_acc), 0);
+}
+
+__global__ __launch_bounds__(256) void k_smerge_b(const Dev *devs, const uint32_t *smap) {
+    smerge_body(devs[smap[blockIdx.x]]);
+}
+
+// =====================================================================
 // k_resolve: replace node codes by final spins in place and measure the
 // configuration (runs once at the end of every sw_sweep call).
 // =====================================================================
@@ -1431,7 +1566,7 @@ __global__ __launch_bounds__(TW *TW / 16) void k_resolve(Dev d) {
 
 template <int TW, bool POTTS = false>
 __global__ __launch_bounds__(TW *TW / 16) void k_resolve_b(const Dev *devs, const uint32_t *map) {
-    const uint32_t e = map[blockIdx.x];
+    const uint32_t e = map[tile_of_block(blockIdx.x, gridDim.x)];
     resolve_body<TW, POTTS>(devs[e >> kMapShift], e & kMapMask);
 }
 
@@ -1552,7 +1687,12 @@ hipError_t launch_resolve(const Dev &d, hipStream_t s) {
 }
 
 hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
-    if (b.n == 0) return hipSuccess;
+    if (b.nall == 0) return hipSuccess;
+    // small replicas: the whole merge in one workgroup each, at stage 1
+    if (b.n == 0 && stage != 0) {
+        if (stage == 1) k_smerge_b<<<b.nsmall, 256, 0, s>>>(b.devs, b.smap);
+        return hipGetLastError();
+    }
     switch (stage) {
     case 0:
         if (b.potts && b.tw == 64)
@@ -1565,6 +1705,7 @@ hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
             k_tile_b<32><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);
         break;
     case 1:
+        if (b.nsmall) k_smerge_b<<<b.nsmall, 256, 0, s>>>(b.devs, b.smap);
         if (b.tw == 64) {
             k_ulocal_b<64><<<b.nugroups, 256, 0, s>>>(b.devs, b.umap);
             k_union_b<64><<<b.nwmap / 2, 256, 0, s>>>(b.devs, b.wmap);
@@ -1597,7 +1738,7 @@ hipError_t launch_batch_sweep(const BatchDev &b, hipStream_t s) {
 }
 
 hipError_t launch_batch_resolve(const BatchDev &b, hipStream_t s) {
-    if (b.n == 0) return hipSuccess;
+    if (b.nall == 0) return hipSuccess;
     if (b.potts && b.tw == 64)
         k_resolve_b<64, true><<<b.ntiles, 256, 0, s>>>(b.devs, b.tmap);
     else if (b.potts)
@@ -1606,7 +1747,7 @@ hipError_t launch_batch_resolve(const BatchDev &b, hipStream_t s) {
         k_resolve_b<64><<<b.ntiles, 256, 0, s>>>(b.devs, b.tmap);
     else
         k_resolve_b<32><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);
-    k_record_b<<<b.n, 256, 0, s>>>(b.devs, b.rmap, 1);
+    k_record_b<<<b.nall, 256, 0, s>>>(b.devs, b.amap, 1);
     return hipGetLastError();
 }
 

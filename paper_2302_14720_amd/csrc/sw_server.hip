@@ -89,27 +89,6 @@ void set_groups(swmi::BatchDev *bd) {
     }
 }
 
-// Work maps of one launch group (see swmi::BatchDev), built on the host.
-struct Maps {
-    std::vector<uint32_t> t, w, g, u, r;
-    void clear() {
-        t.clear();
-        w.clear();
-        g.clear();
-        u.clear();
-        r.clear();
-    }
-    void add(uint32_t slot, const Dev &d) {
-        const uint32_t tag = slot << swmi::kMapShift;
-        r.push_back(slot);
-        for (uint32_t i = 0; i < d.ntiles; ++i) t.push_back(tag | i);
-        for (uint32_t i = 0; i < d.ngroups; ++i) g.push_back(tag | i);
-        const uint32_t ngx = (d.ntx + swmi::kUG - 1u) / swmi::kUG;
-        for (uint32_t i = 0; i < ngx * ngx; ++i) u.push_back(tag | i);
-    }
-    size_t entries() const { return t.size() + ((t.size() + 3u) & ~size_t(3)) + g.size() + u.size() + r.size(); }
-};
-
 }  // namespace
 
 struct sw_server {
@@ -144,9 +123,9 @@ int srv_device(const sw_server *s) {
 
 // Copies the maps of the launch groups into the device map buffer and
 // points the BatchDevs at them.  The stream is idle when this runs.
-int upload_maps(sw_server *s, Maps *m, swmi::BatchDev *bd, int ngroups) {
+int upload_maps(sw_server *s, swmi::BatchMaps *m, swmi::BatchDev *bd, int ngroups) {
     size_t need = 0;
-    for (int i = 0; i < ngroups; ++i) need += m[i].entries();
+    for (int i = 0; i < ngroups; ++i) need += m[i].words();
     if (need > s->maps_cap) {
         if (s->d_maps) (void)hipFree(s->d_maps);
         s->d_maps = nullptr;
@@ -162,28 +141,8 @@ int upload_maps(sw_server *s, Maps *m, swmi::BatchDev *bd, int ngroups) {
     std::vector<uint32_t> host;
     host.reserve(need);
     for (int i = 0; i < ngroups; ++i) {
-        Maps &mm = m[i];
-        swmi::BatchDev &b = bd[i];
-        b.devs = s->d_devs;
-        b.n = (uint32_t)mm.r.size();
-        b.ntiles = (uint32_t)mm.t.size();
-        b.ngroups = (uint32_t)mm.g.size();
-        b.nugroups = (uint32_t)mm.u.size();
-        b.nwmap = (b.ntiles + 3u) & ~3u;
-        std::vector<uint32_t> w = mm.t;
-        w.resize(b.nwmap, swmi::kMapNone);
-        const size_t at = host.size();
-        host.insert(host.end(), mm.t.begin(), mm.t.end());
-        host.insert(host.end(), w.begin(), w.end());
-        host.insert(host.end(), mm.g.begin(), mm.g.end());
-        host.insert(host.end(), mm.u.begin(), mm.u.end());
-        host.insert(host.end(), mm.r.begin(), mm.r.end());
-        uint32_t *base = s->d_maps + at;
-        b.tmap = base;
-        b.wmap = base + b.ntiles;
-        b.gmap = base + b.ntiles + b.nwmap;
-        b.umap = base + b.ntiles + b.nwmap + b.ngroups;
-        b.rmap = base + b.ntiles + b.nwmap + b.ngroups + b.nugroups;
+        bd[i].devs = s->d_devs;
+        m[i].emit(host, s->d_maps, bd[i]);
     }
     if (!host.empty()) HIP_TRY(hipMemcpy(s->d_maps, host.data(), host.size() * 4, hipMemcpyHostToDevice));
     return SW_OK;
@@ -191,8 +150,8 @@ int upload_maps(sw_server *s, Maps *m, swmi::BatchDev *bd, int ngroups) {
 
 int rebuild_active(sw_server *s) {
     HIP_TRY(hipStreamSynchronize(s->stream));
-    Maps m[kGroups];
-    for (Job *j : s->active) m[group_of(j->dev)].add((uint32_t)j->slot, j->dev);
+    swmi::BatchMaps m[kGroups];
+    for (Job *j : s->active) m[group_of(j->dev)].add((uint32_t)j->slot, j->dev, true);
     set_groups(s->bd);
     const int rc = upload_maps(s, m, s->bd, kGroups);
     if (rc == SW_OK) s->dirty = false;
@@ -372,9 +331,9 @@ int sw_server_step(sw_server *s, int64_t n, int64_t *done_ids, int32_t cap, int3
         for (Job *j : s->active) (j->done == j->target ? fin : keep).push_back(j);
         if (fin.empty()) continue;
         HIP_TRY(hipStreamSynchronize(s->stream));
-        Maps m[kGroups];
+        swmi::BatchMaps m[kGroups];
         swmi::BatchDev rb[kGroups]{};
-        for (Job *j : fin) m[group_of(j->dev)].add((uint32_t)j->slot, j->dev);
+        for (Job *j : fin) m[group_of(j->dev)].add((uint32_t)j->slot, j->dev, true);
         set_groups(rb);
         rc = upload_maps(s, m, rb, kGroups);
         if (rc != SW_OK) return rc;

@@ -86,6 +86,15 @@ def test_batch_workspace_sizes_and_validation():
     assert sw.sw_batch_workspace_bytes(np.array([64, 100], dtype=np.int32)) == 0
     assert sw.sw_batch_workspace_bytes(np.zeros(0, dtype=np.int32)) == 0
     assert sw.sw_batch_workspace_bytes(np.full(4097, 64, dtype=np.int32)) == 0
+    # per-replica tile widths and merges
+    mixed = np.array([64, 96, 512], dtype=np.int32)
+    assert sw.sw_batch_workspace_bytes(mixed, tiles=[64, 32, 64], merge=[1, 1, 2]) > 0
+    assert sw.sw_batch_workspace_bytes(mixed, tiles=[64, 64, 64]) == 0  # 96 needs 32-wide tiles
+    assert "replica 1" in sw.sw_last_error()
+    assert sw.sw_batch_workspace_bytes(mixed, merge=[0, 0, sw.SW_MERGE_LDS]) == 0  # 64 tiles: too many for LDS
+    assert "LDS merge" in sw.sw_last_error()
+    assert sw.sw_batch_workspace_bytes(mixed, merge=[0, 3, 0]) == 0
+    assert sw.sw_batch_workspace_bytes(mixed, q=[0, 3, 9], tiles=0) == 0
     # creation is refused before any device call for invalid replicas
     h = ctypes.c_void_p()
     b = np.array([0.4, 0.4]), np.array([1.0, 1.0])

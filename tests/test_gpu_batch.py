@@ -67,7 +67,7 @@ def test_tile32_batch_and_cold_start():
     beta = [0.35, BETA_C, 0.5, BETA_C]
     seed = [21, 22, 23, 24]
     n = 20
-    with _batch(L, beta, seed, init=sw.SW_INIT_COLD) as b:
+    with _batch(L, beta, seed, init=sw.SW_INIT_COLD, tile=32) as b:
         assert b.tile == 32
         b.sweep(n)
         for r in range(len(L)):
@@ -153,7 +153,7 @@ def test_autotuner_picks_an_allowed_tile(tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("qs,L,want_tile", [
     ([2, 3, 4, 3, 2], [64, 128, 192, 64, 256], 64),        # q <= 4, multiples of 64
-    ([3, 5, 8, 2], [64, 96, 128, 160], 32),                # q above 4 or L % 64 != 0
+    ([3, 5, 8, 2], [64, 96, 128, 160], 0),                 # q above 4 or L % 64 != 0: mixed widths
 ])
 def test_potts_batch_matches_plain_and_oracle(qs, L, want_tile):
     """A batch of Potts replicas (mixed q and L): every replica's records and
@@ -171,7 +171,7 @@ def test_potts_batch_matches_plain_and_oracle(qs, L, want_tile):
         for r in range(n):
             assert b.threshold(r) == oracle.potts_threshold(beta[r], 1.0)
             got = b.series(r, 0, sweeps)
-            with sw.Sim(L[r], beta[r], 1.0, seed[r], q=qs[r], tile=want_tile) as s:
+            with sw.Sim(L[r], beta[r], 1.0, seed[r], q=qs[r], tile=b.replica_tile(r)) as s:
                 s.sweep(sweeps)
                 ref, sp = s.series(0, sweeps), s.spins()
             _same_records(got, ref, f"replica {r}")
@@ -191,3 +191,77 @@ def test_potts_batch_errors():
     with pytest.raises(sw.SwError) as e:
         sw.Batch([64, 128], 0.5, 1.0, [1, 2], q=[3, 6], tile=64)
     assert e.value.code == sw.SW_EINVAL
+
+
+def test_per_replica_tiles_and_merges_match_plain():
+    """Replicas with their own tile width and merge (LDS-resident or global),
+    Ising and Potts in one batch: four launch groups, every replica's bits
+    those of a plain sim; the same table with every merge global gives the
+    same bits."""
+    L = [64, 96, 128, 256, 512, 64, 128, 192]
+    q = [0, 0, 0, 0, 0, 3, 5, 2]
+    tiles = [64, 32, 32, 64, 64, 64, 32, 64]
+    merge = [sw.SW_MERGE_LDS, sw.SW_MERGE_AUTO, sw.SW_MERGE_GLOBAL, sw.SW_MERGE_LDS, sw.SW_MERGE_AUTO,
+             sw.SW_MERGE_LDS, sw.SW_MERGE_LDS, sw.SW_MERGE_GLOBAL]
+    beta = [BETA_C, 0.3, 0.6, BETA_C, 0.45, 1.0050525, 0.9, 0.5]
+    seed = [700 + i for i in range(len(L))]
+    n = 15
+    with _batch(L, beta, seed, q=q, tiles=tiles, merge=merge) as b, \
+            _batch(L, beta, seed, q=q, tiles=tiles, merge=sw.SW_MERGE_GLOBAL) as g:
+        assert b.tile == 0
+        want_merge = [sw.SW_MERGE_LDS, sw.SW_MERGE_LDS, sw.SW_MERGE_GLOBAL, sw.SW_MERGE_LDS, sw.SW_MERGE_GLOBAL,
+                      sw.SW_MERGE_LDS, sw.SW_MERGE_LDS, sw.SW_MERGE_GLOBAL]
+        for r in range(len(L)):
+            assert b.replica_tile(r) == tiles[r] and b.replica_merge(r) == want_merge[r], f"replica {r}"
+            assert g.replica_merge(r) == sw.SW_MERGE_GLOBAL
+        b.sweep(4)
+        b.sweep(n - 4)
+        g.sweep(n)
+        for r in range(len(L)):
+            got = b.series(r, 0, n)
+            with sw.Sim(L[r], beta[r], 1.0, seed[r], q=q[r], tile=tiles[r]) as s:
+                s.sweep(n)
+                ref, sp = s.series(0, n), s.spins()
+            _same_records(got, ref, f"replica {r}")
+            _same_records(g.series(r, 0, n), ref, f"replica {r}, global merge")
+            assert np.array_equal(b.spins(r), sp), f"replica {r} spins"
+            assert np.array_equal(g.spins(r), sp), f"replica {r} spins, global merge"
+
+
+def test_lds_merge_on_giant_and_empty_clusters():
+    """The LDS merge at the extremes: a cold start (one cluster spanning every
+    tile of a 16-tile replica), beta = 0 (no bonds: only tile-interior
+    clusters), and a replica of one tile (every edge wraps onto itself)."""
+    L = [256, 256, 64, 128]
+    beta = [BETA_C, 0.0, 5.0, 3.0]
+    seed = [801, 802, 803, 804]
+    n = 6
+    for init in (sw.SW_INIT_COLD, sw.SW_INIT_HOT):
+        with _batch(L, beta, seed, init=init, merge=sw.SW_MERGE_LDS) as b:
+            b.sweep(n)
+            for r in range(len(L)):
+                assert b.replica_merge(r) == sw.SW_MERGE_LDS
+                ref, sp = _plain(L[r], beta[r], seed[r], n, cold=init == sw.SW_INIT_COLD)
+                _same_records(b.series(r, 0, n), ref, f"init {init} replica {r}")
+                assert np.array_equal(b.spins(r), sp), f"init {init} replica {r} spins"
+
+
+def test_per_side_autotuner_choices(tmp_path, monkeypatch):
+    """The per-side tuner returns, for every replica, a tile width and a
+    merge that the replica allows, caches them, and the batch built from
+    them runs (its bits are covered by the per-replica test above)."""
+    from paper_2302_14720_amd import autotune
+
+    monkeypatch.setenv("SWMI_TUNE_CACHE", str(tmp_path / "tune.json"))
+    L = [64, 256, 96, 64, 512]
+    q = [0, 0, 0, 3, 0]
+    tiles, merges, table = autotune.tune_batch_per_side(L, 0.44, 1.0, [1, 2, 3, 4, 5], q=q, sweeps=3, warmup=1)
+    for r in range(len(L)):
+        assert (int(tiles[r]), int(merges[r])) in autotune._options(L[r], q[r]), f"replica {r}"
+        assert (L[r], q[r]) in table
+    assert int(tiles[2]) == 32 and int(merges[4]) == sw.SW_MERGE_GLOBAL
+    again = autotune.tune_batch_per_side(L, 0.44, 1.0, [1, 2, 3, 4, 5], q=q)
+    assert np.array_equal(again[0], tiles) and np.array_equal(again[1], merges)
+    with _batch(L, 0.44, [1, 2, 3, 4, 5], q=q, tiles=tiles, merge=merges) as b:
+        b.sweep(3)
+        assert int(b.observables()[0]["sweep"]) == 2

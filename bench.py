@@ -132,12 +132,13 @@ def batched_vs_plain(args):
 
     L, beta, seed = grid_table(256, 1000)
     sites = int((L.astype("int64") ** 2).sum())
-    tiles, merges, tune_ms = autotune.tune_batch_per_side(L, beta, 1.0, seed, sweeps=10, use_cache=False)
+    tiles, merges, tune = autotune.tune_batch_table(L, beta, 1.0, seed, sweeps=10, use_cache=False)
+    tune_ms = tune["per_side"]
     choice = {int(side): {"tile": int(tiles[L == side][0]),
                           "merge": "lds" if int(merges[L == side][0]) == sw.SW_MERGE_LDS else "global"}
               for side in sorted(set(L.tolist()))}
-    print(f"[bench] batched: {len(L)} replicas, {sites} sites; autotuned per side {choice}",
-          file=sys.stderr, flush=True)
+    print(f"[bench] batched: {len(L)} replicas, {sites} sites; autotuned {tune['choice']}: {choice} "
+          f"(whole-table candidates, ms per sweep: {tune['batch']})", file=sys.stderr, flush=True)
     b = sw.Batch(L, beta, 1.0, seed, tiles=tiles, merge=merges)
     b.sweep(args.warmup)
     b.sync()
@@ -183,7 +184,8 @@ def batched_vs_plain(args):
     return {
         "workload": "256 replicas, L = {64,128,256,512,1024}[r mod 5], beta_k = 0.40 + 0.08 k/31 "
                     "(k = r // 8), seed 1000 + r, hot start, J = 1",
-        "replicas": len(L), "sites": sites, "per_side": choice,
+        "replicas": len(L), "sites": sites, "per_side": choice, "autotune_choice": tune["choice"],
+        "autotune_table_ms_per_sweep": tune["batch"],
         "autotune_ms_per_sweep": {f"L={k[0]}": {f"tile{t}_{'lds' if m == sw.SW_MERGE_LDS else 'global'}": v
                                                 for (t, m), v in ms.items()} for k, ms in tune_ms.items()},
         "value": bval, "unit": "site-updates/s", "sweeps": args.batch_steps,

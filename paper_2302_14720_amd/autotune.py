@@ -147,3 +147,40 @@ def tune_batch_per_side(L, beta, J=1.0, seed=0, q=None, *, sweeps: int = 10, war
         tiles[idx], merges[idx] = best
         table[(side, qq)] = ms
     return tiles, merges, table
+
+
+def tune_batch_table(L, beta, J=1.0, seed=0, q=None, *, sweeps: int = 10, warmup: int = 3,
+                     use_cache: bool = True):
+    """Tile side and merge for every replica of a table: the per-side choices
+    of tune_batch_per_side, then a check on the whole table against the same
+    tiles with every merge global and against the widest allowed tile with
+    either merge rule (a side that is fastest alone may cost the mixed batch
+    an extra launch group or a longer merge).  Returns (tiles, merges,
+    {"per_side": ..., "batch": {name: ms per sweep}, "choice": name})."""
+    La = np.asarray(L, dtype=np.int32)
+    n = La.size
+    ba = np.broadcast_to(np.asarray(beta, dtype=np.float64), (n,))
+    Ja = np.broadcast_to(np.asarray(J, dtype=np.float64), (n,))
+    sa = np.broadcast_to(np.asarray(seed, dtype=np.uint64), (n,))
+    qa = np.zeros(n, dtype=np.int32) if q is None else np.broadcast_to(np.asarray(q, dtype=np.int32), (n,))
+    tiles, merges, per_side = tune_batch_per_side(La, ba, Ja, sa, q=qa, sweeps=sweeps, warmup=warmup,
+                                                  use_cache=use_cache)
+    wide = np.where((La % 64 == 0) & (qa <= 4), 64, 32).astype(np.int32)
+    cands = {
+        "per_side": (tiles, merges),
+        "per_side_tiles_global_merge": (tiles, np.full(n, SW_MERGE_GLOBAL, dtype=np.int32)),
+        "widest_tiles_auto_merge": (wide, np.zeros(n, dtype=np.int32)),
+        "widest_tiles_global_merge": (wide, np.full(n, SW_MERGE_GLOBAL, dtype=np.int32)),
+    }
+    digest = hashlib.sha1(La.tobytes() + qa.tobytes()).hexdigest()[:16]
+    key = f"{_device()}|batch-table|n={n}|{digest}"
+    hit = _load().get(key) if use_cache else None
+    if hit and hit.get("choice") in cands:
+        ms, choice = hit["ms"], hit["choice"]
+    else:
+        ms = {name: _time(lambda t=t, m=m: Batch(La, ba, Ja, sa, init=SW_INIT_HOT, ring=64, q=qa, tiles=t, merge=m),
+                          warmup, sweeps) for name, (t, m) in cands.items()}
+        choice = min(ms, key=ms.get)
+        _store(key, {"choice": choice, "ms": ms})
+    t, m = cands[choice]
+    return t, m, {"per_side": per_side, "batch": ms, "choice": choice}

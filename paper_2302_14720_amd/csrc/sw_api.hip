@@ -595,6 +595,11 @@ struct sw_batch {
     swmi::BatchDev bd[kBatchGroups];
     hipStream_t stream;
     bool own_stream;
+    // the LDS merges run on a second stream (default priority) beside the
+    // global merge, forked after the tile kernels and joined before the
+    // next sweep
+    hipStream_t side;
+    hipEvent_t fork, join;
     void *ws;
     size_t ws_bytes;
     bool own_ws;
@@ -694,11 +699,24 @@ void batch_drop_graph(sw_batch *b) {
 }
 
 hipError_t batch_launch_sweep(const sw_batch *b) {
+    bool small = false, large = false;
     for (int g = 0; g < kBatchGroups; ++g) {
-        const hipError_t e = swmi::launch_batch_sweep(b->bd[g], b->stream);
-        if (e != hipSuccess) return e;
+        small = small || b->bd[g].nsmall > 0;
+        large = large || b->bd[g].n > 0;
     }
-    return hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int g = 0; g < kBatchGroups && e == hipSuccess; ++g) e = swmi::launch_batch_stage(b->bd[g], 0, b->stream);
+    // the LDS merges beside the global merge when both kinds are present
+    const bool fork = small && large && b->side != nullptr;
+    hipStream_t ss = fork ? b->side : b->stream;
+    if (e == hipSuccess && fork) e = hipEventRecord(b->fork, b->stream);
+    if (e == hipSuccess && fork) e = hipStreamWaitEvent(b->side, b->fork, 0);
+    for (int g = 0; g < kBatchGroups && e == hipSuccess; ++g) e = swmi::launch_batch_smerge(b->bd[g], ss);
+    for (int stage = 1; stage < swmi::kStages && e == hipSuccess; ++stage)
+        for (int g = 0; g < kBatchGroups && e == hipSuccess; ++g) e = swmi::launch_batch_stage(b->bd[g], stage, b->stream);
+    if (e == hipSuccess && fork) e = hipEventRecord(b->join, b->side);
+    if (e == hipSuccess && fork) e = hipStreamWaitEvent(b->stream, b->join, 0);
+    return e;
 }
 
 // One batched sweep captured as a graph; on any capture failure the kernels
@@ -791,6 +809,16 @@ int batch_create(int32_t n, const int32_t *L, const double *beta, const double *
                 return hip_fail(e, "hipStreamCreateWithFlags");
             }
             b->own_stream = true;
+        }
+    }
+    if (b->stream != nullptr) {  // (the legacy null stream runs everything in order on itself)
+        e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "creating the batch's second stream");
+            sw_batch_destroy(b);
+            return rc;
         }
     }
     char *base = (char *)b->ws;
@@ -1009,6 +1037,12 @@ void sw_batch_destroy(sw_batch *b) {
     (void)batch_device(b);
     (void)hipStreamSynchronize(b->stream);
     batch_drop_graph(b);
+    if (b->side) {
+        (void)hipStreamSynchronize(b->side);
+        (void)hipStreamDestroy(b->side);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
     if (b->own_ws && b->ws) (void)hipFree(b->ws);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;

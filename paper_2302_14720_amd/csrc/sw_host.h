@@ -40,7 +40,7 @@ Dev make_dev(const sw_config &c, char *base, const Layout &lo);
 // and it has at most kSmallTiles tiles; emit() appends the maps to `host`
 // (which will be copied to dev_base) and points the BatchDev at them.
 struct BatchMaps {
-    std::vector<uint32_t> t, w, g, u, r, s, a;
+    std::vector<uint32_t> t, w, wn, g, u, r, s, a;  // w / wn: tiles with an E / N group edge
     void add(uint32_t slot, const Dev &d, bool small) {
         const uint32_t tag = slot << kMapShift;
         a.push_back(slot);
@@ -50,18 +50,26 @@ struct BatchMaps {
             return;
         }
         r.push_back(slot);
-        for (uint32_t i = 0; i < d.ntiles; ++i) w.push_back(tag | i);
+        // edges between kUG x kUG groups of tiles (those inside a group are
+        // joined by k_ulocal): the last tile column / row of every group
+        for (uint32_t i = 0; i < d.ntiles; ++i) {
+            const uint32_t tx = i % d.ntx, ty = i / d.ntx;
+            if (tx % kUG == kUG - 1u || tx + 1u == d.ntx) w.push_back(tag | i);
+            if (ty % kUG == kUG - 1u || ty + 1u == d.ntx) wn.push_back(tag | i);
+        }
         for (uint32_t i = 0; i < d.ngroups; ++i) g.push_back(tag | i);
         const uint32_t ngx = (d.ntx + kUG - 1u) / kUG;
         for (uint32_t i = 0; i < ngx * ngx; ++i) u.push_back(tag | i);
     }
     size_t words() const {
-        return t.size() + ((w.size() + 3u) & ~size_t(3)) + g.size() + u.size() + r.size() + s.size() + a.size();
+        return t.size() + ((w.size() + wn.size() + 3u) & ~size_t(3)) + g.size() + u.size() + r.size() + s.size() +
+               a.size();
     }
     void emit(std::vector<uint32_t> &host, const uint32_t *dev_base, BatchDev &b) const {
         const size_t at = host.size();
         b.ntiles = (uint32_t)t.size();
-        b.nwmap = (uint32_t)((w.size() + 3u) & ~size_t(3));
+        b.nwmap = (uint32_t)((w.size() + wn.size() + 3u) & ~size_t(3));
+        b.nwE = (uint32_t)w.size();
         b.ngroups = (uint32_t)g.size();
         b.nugroups = (uint32_t)u.size();
         b.n = (uint32_t)r.size();
@@ -69,6 +77,7 @@ struct BatchMaps {
         b.nall = (uint32_t)a.size();
         host.insert(host.end(), t.begin(), t.end());
         host.insert(host.end(), w.begin(), w.end());
+        host.insert(host.end(), wn.begin(), wn.end());
         host.resize(at + b.ntiles + b.nwmap, kMapNone);
         host.insert(host.end(), g.begin(), g.end());
         host.insert(host.end(), u.begin(), u.end());

@@ -109,14 +109,14 @@ constexpr uint32_t kSmallTiles = 16;
 struct BatchDev {
     const Dev *devs;       // the replicas' Dev, in device memory
     const uint32_t *tmap;  // [ntiles] one entry per tile of every replica (k_tile, k_resolve)
-    const uint32_t *wmap;  // [nwmap] one per wavefront of k_union, kMapNone-padded to 4
+    const uint32_t *wmap;  // [nwmap] tiles with an E (first nwE) or N group edge (k_union), kMapNone-padded to 4
     const uint32_t *gmap;  // [ngroups] one per group of kGroupTiles tiles (k_flatten, k_roots)
     const uint32_t *umap;  // [nugroups] one per kUG x kUG group of tiles (k_ulocal)
     const uint32_t *rmap;  // [n] the replicas (indices into devs) of the global merge
     const uint32_t *smap;  // [nsmall] the replicas merged in LDS
     const uint32_t *amap;  // [nall] every replica of the launch (records after k_resolve)
     uint32_t n, ntiles, nwmap, ngroups, nugroups, tw;
-    uint32_t nsmall, nall;
+    uint32_t nwE, nsmall, nall;
     uint32_t potts;        // 1: every replica is a Potts model (q in its Dev)
 };
 
@@ -131,7 +131,12 @@ constexpr uint32_t kLeChunk = 4096;  // sites per workgroup in the per-site pass
 constexpr uint32_t kBrick = 16;      // side of a brick of the simple cubic lattice
 enum { LE_PASSES = 3, LE_STATUS = 4 };
 
+// Stage 0 is the tile kernel of every replica; stages 1..4 the global merge;
+// launch_batch_smerge the LDS merge of the small replicas, which may run
+// beside stages 1..4 once stage 0 is done.  launch_batch_sweep runs them
+// all in order on one stream.
 hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s);
+hipError_t launch_batch_smerge(const BatchDev &b, hipStream_t s);
 hipError_t launch_batch_sweep(const BatchDev &b, hipStream_t s);
 hipError_t launch_batch_resolve(const BatchDev &b, hipStream_t s);
 

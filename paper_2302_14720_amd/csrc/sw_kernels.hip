@@ -899,11 +899,14 @@ __global__ __launch_bounds__(256) void k_union(Dev d) {
     }
 }
 
+// One wavefront per map entry: the first nE entries are tiles whose E edge
+// is a group edge, the rest tiles whose N edge is (kMapNone pads the map to
+// whole workgroups).
 template <int TW>
-__global__ __launch_bounds__(256) void k_union_b(const Dev *devs, const uint32_t *map) {
+__global__ __launch_bounds__(256) void k_union_b(const Dev *devs, const uint32_t *map, uint32_t nE) {
     const uint32_t w = blockIdx.x * 4u + (threadIdx.x >> 6);
-    const uint32_t e = map[w / 2u];
-    if (e != kMapNone) union_body<TW>(devs[e >> kMapShift], e & kMapMask, w & 1u);
+    const uint32_t e = map[w];
+    if (e != kMapNone) union_body<TW>(devs[e >> kMapShift], e & kMapMask, w < nE ? 0u : 1u);
 }
 
 // =====================================================================
@@ -933,9 +936,15 @@ __device__ __forceinline__ void hash_add(uint32_t *hk, uint32_t *hv, uint32_t *h
         h = (h + 1u) & (kHashSlots - 1);
     }
     atomicAdd(&d.nsize[root], size);
-    atomicMin(&d.key[root], key);
+    if (key < g_load(&d.key[root])) atomicMin(&d.key[root], key);
 }
 
+// FT tiles per workgroup: a root gets one atomic of each kind per workgroup
+// that holds some of its nodes, so a cluster that spans the lattice receives
+// ntiles / FT of them, one after the other; plain lattices take 64, batches
+// their 16-tile groups.  A key minimum is skipped when a plain read already
+// shows a key no larger (keys only decrease).
+template <uint32_t FT>
 __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group) {
     __shared__ uint32_t hk[kHashSlots];
     __shared__ uint32_t hv[kHashSlots];
@@ -949,16 +958,17 @@ __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group)
     const uint32_t pc = (uint32_t)(*d.tdev & 1u);
     uint32_t *par = d.parent[pc];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint32_t g0 = group * (uint32_t)kGroupTiles;
-    // wavefront wv owns tiles g0 + wv + 4q (q < 4); their nodes are numbered
-    // one after the other (about 80 per tile at beta_c, so mostly one batch),
-    // and each lane chases the roots of up to 8 nodes at once, one level per
-    // round, so their loads overlap
-    static_assert(kGroupTiles == 16, "four tiles per wavefront");
+    const uint32_t g0 = group * FT;
+    static_assert(FT % 16u == 0u, "four tiles per wavefront and quad");
+    // wavefront wv owns tiles g0 + wv + 4q, taken four at a time (a quad);
+    // the nodes of a quad are numbered one after the other (about 80 per
+    // tile at beta_c, so mostly one batch), and each lane chases the roots
+    // of up to 8 nodes at once, one level per round, so their loads overlap
+    for (uint32_t quad = 0; quad < FT / 16u; ++quad) {
     uint32_t nkq[4];
 #pragma unroll
     for (uint32_t q = 0; q < 4u; ++q) {
-        const uint32_t tile = g0 + wv + 4u * q;
+        const uint32_t tile = g0 + wv + 4u * (4u * quad + q);
         const uint32_t v = d.nk[pc][min(tile, d.ntiles - 1u)];  // issued unconditionally
         nkq[q] = tile < d.ntiles ? min(v, 252u) : 0u;
     }
@@ -973,7 +983,7 @@ __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group)
             const uint32_t i = lane + 64u * (m0 + j);
             const uint32_t q = (uint32_t)(i >= pre1) + (uint32_t)(i >= pre2) + (uint32_t)(i >= pre3);
             const uint32_t base = q == 0u ? 0u : q == 1u ? pre1 : q == 2u ? pre2 : pre3;
-            nd[j] = i < tot ? (g0 + wv + 4u * q) * kNodeSlots + (i - base) : kEmpty;
+            nd[j] = i < tot ? (g0 + wv + 4u * (4u * quad + q)) * kNodeSlots + (i - base) : kEmpty;
             r[j] = nd[j];
         }
         bool more = true;
@@ -998,21 +1008,24 @@ __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group)
             hash_add(hk, hv, hm, r[j], d.nsize[nd[j]], d.key[nd[j]], d);
         }
     }
+    }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < (uint32_t)kHashSlots; i += 256u) {
         const uint32_t k = hk[i];
         if (k != kEmpty) {
             atomicAdd(&d.nsize[k], hv[i]);
-            atomicMin(&d.key[k], hm[i]);
+            if (hm[i] < g_load(&d.key[k])) atomicMin(&d.key[k], hm[i]);
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_flatten(Dev d) { flatten_body(d, blockIdx.x); }
+constexpr uint32_t kFlatTiles = 64;  // tiles per workgroup of k_flatten (plain lattices)
+
+__global__ __launch_bounds__(256) void k_flatten(Dev d) { flatten_body<kFlatTiles>(d, blockIdx.x); }
 
 __global__ __launch_bounds__(256) void k_flatten_b(const Dev *devs, const uint32_t *map) {
     const uint32_t e = map[blockIdx.x];
-    flatten_body(devs[e >> kMapShift], e & kMapMask);
+    flatten_body<kGroupTiles>(devs[e >> kMapShift], e & kMapMask);
 }
 
 // Canonical labels of sites of cross-tile clusters (only with SW_FLAG_LABELS).
@@ -1649,7 +1662,7 @@ hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
         break;
     }
     case 2:  // flatten + cluster sizes
-        k_flatten<<<d.ngroups, 256, 0, s>>>(d);
+        k_flatten<<<(d.ntiles + kFlatTiles - 1u) / kFlatTiles, 256, 0, s>>>(d);
         if (d.labels) k_relabel<<<grid_for(n, 256, 65536), 256, 0, s>>>(d);
         break;
     case 3:  // spins of cross-tile clusters, statistics
@@ -1686,13 +1699,15 @@ hipError_t launch_resolve(const Dev &d, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_batch_smerge(const BatchDev &b, hipStream_t s) {
+    if (b.nsmall == 0) return hipSuccess;
+    k_smerge_b<<<b.nsmall, 256, 0, s>>>(b.devs, b.smap);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
     if (b.nall == 0) return hipSuccess;
-    // small replicas: the whole merge in one workgroup each, at stage 1
-    if (b.n == 0 && stage != 0) {
-        if (stage == 1) k_smerge_b<<<b.nsmall, 256, 0, s>>>(b.devs, b.smap);
-        return hipGetLastError();
-    }
+    if (b.n == 0 && stage != 0) return hipSuccess;  // stages 1..4: replicas of the global merge
     switch (stage) {
     case 0:
         if (b.potts && b.tw == 64)
@@ -1705,13 +1720,12 @@ hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
             k_tile_b<32><<<b.ntiles, 64, 0, s>>>(b.devs, b.tmap);
         break;
     case 1:
-        if (b.nsmall) k_smerge_b<<<b.nsmall, 256, 0, s>>>(b.devs, b.smap);
         if (b.tw == 64) {
             k_ulocal_b<64><<<b.nugroups, 256, 0, s>>>(b.devs, b.umap);
-            k_union_b<64><<<b.nwmap / 2, 256, 0, s>>>(b.devs, b.wmap);
+            k_union_b<64><<<b.nwmap / 4, 256, 0, s>>>(b.devs, b.wmap, b.nwE);
         } else {
             k_ulocal_b<32><<<b.nugroups, 256, 0, s>>>(b.devs, b.umap);
-            k_union_b<32><<<b.nwmap / 2, 256, 0, s>>>(b.devs, b.wmap);
+            k_union_b<32><<<b.nwmap / 4, 256, 0, s>>>(b.devs, b.wmap, b.nwE);
         }
         break;
     case 2:
@@ -1731,7 +1745,8 @@ hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
 
 hipError_t launch_batch_sweep(const BatchDev &b, hipStream_t s) {
     for (int stage = 0; stage < kStages; ++stage) {
-        const hipError_t e = launch_batch_stage(b, stage, s);
+        hipError_t e = launch_batch_stage(b, stage, s);
+        if (e == hipSuccess && stage == 0) e = launch_batch_smerge(b, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

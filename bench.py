@@ -83,8 +83,12 @@ def load_counters(L: int):
     return d
 
 
-# VALU issue ceiling: one wave64 instruction per SIMD every 2 clocks
-VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2
+# Instruction-throughput ceilings of the chip for wave64 integer work, as
+# measured by throughput probes (independent add/xor chains: 1.35 VALU
+# wave-instructions per CU per clock; scalar chains: 0.86 SALU per CU per
+# clock, issued beside the VALU), at the 2.4 GHz clock.
+VALU_ISSUE_PEAK = 256 * 2.4e9 * 1.35
+SALU_ISSUE_PEAK = 256 * 2.4e9 * 0.86
 
 
 def cpu_baseline(args):
@@ -603,6 +607,7 @@ def main() -> int:
     cnt = load_counters(L)
     traffic = cnt.get("hbm_bytes_per_launch") if (cnt and dom == "tile") else None
     valu = cnt.get("valu_wave_instructions_per_launch") if (cnt and dom == "tile") else None
+    salu = cnt.get("salu_wave_instructions_per_launch") if (cnt and dom == "tile") else None
     alu_ach = (0.5 + 1.0 / tw) * PHILOX_OPS * N / t_dom / 1e12
     design_ach = TILE_BYTES_PER_SITE * N / t_dom / 1e9
     roofline = {
@@ -622,6 +627,7 @@ def main() -> int:
             "design_hbm_frac": design_ach / HBM_PEAK_GBS,
             "philox_alu_Tops": alu_ach, "philox_alu_frac": alu_ach / ALU_PEAK_TOPS,
             "valu_issue_frac": (valu / t_dom / VALU_ISSUE_PEAK) if valu else None,
+            "salu_issue_frac": (salu / t_dom / SALU_ISSUE_PEAK) if salu else None,
         },
     }
     # measured HBM bytes of every kernel of a sweep (committed counters of the

@@ -823,13 +823,10 @@ __device__ __forceinline__ void ulocal_body(const Dev &d, const uint32_t ugroup)
     const uint32_t gx = ugroup % ngx, gy = ugroup / ngx;
     auto tile_of = [&](uint32_t t) { return (gy * kUG + t / kUG) * ntx + gx * kUG + t % kUG; };
     auto valid = [&](uint32_t t) { return gx * kUG + t % kUG < ntx && gy * kUG + t / kUG < ntx; };
-    if (tid < NG) s_nk[tid] = valid(tid) ? min(d.nk[pc][tile_of(tid)], 252u) : 0u;
-    for (uint32_t i = tid; i < NG * kNodeSlots; i += 256u) s_p[i] = i;
-    __syncthreads();
-
     // tile-edges inside the group: E edges (lx < kUG-1), then N edges (ly <
     // kUG-1), one position per thread and iteration; all of a thread's loads
-    // are issued before its unions
+    // are issued first (they do not depend on the sweep parity), then the
+    // node counts, then the unions
     constexpr uint32_t NE = (kUG - 1u) * kUG;
     constexpr uint32_t NIT = 2u * NE * TW / 256u;
     static_assert(2u * NE * TW % 256u == 0u, "edge positions must fill the workgroup");
@@ -849,6 +846,9 @@ __device__ __forceinline__ void ulocal_body(const Dev &d, const uint32_t ugroup)
         ua[it] = ta * kNodeSlots + (isn ? ea[3 * TW + i] : ea[1 * TW + i]);
         ub[it] = tb * kNodeSlots + (isn ? eb[2 * TW + i] : eb[0 * TW + i]);
     }
+    if (tid < NG) s_nk[tid] = valid(tid) ? min(d.nk[pc][tile_of(tid)], 252u) : 0u;
+    for (uint32_t i = tid; i < NG * kNodeSlots; i += 256u) s_p[i] = i;
+    __syncthreads();
 #pragma unroll
     for (uint32_t it = 0; it < NIT; ++it) {
         const uint32_t i = (tid + 256u * it) % TW, a = ua[it], b = ub[it];
@@ -918,6 +918,13 @@ __global__ __launch_bounds__(256) void k_union_b(const Dev *devs, const uint32_t
 // =====================================================================
 constexpr int kHashSlots = 2048;
 
+// Node count of tile i in the sweep of parity pc: both parities are loaded,
+// so that the loads need not wait for the sweep index.
+__device__ __forceinline__ uint32_t nk_either(const Dev &d, uint32_t pc, uint32_t i) {
+    const uint32_t a = d.nk[0][i], b = d.nk[1][i];
+    return pc ? b : a;
+}
+
 __device__ __forceinline__ void hash_add(uint32_t *hk, uint32_t *hv, uint32_t *hm, uint32_t root, uint32_t size,
                                          uint32_t key, const Dev &d) {
     uint32_t h = (root * 2654435761u) >> 21;  // 11 bits
@@ -939,11 +946,11 @@ __device__ __forceinline__ void hash_add(uint32_t *hk, uint32_t *hv, uint32_t *h
     if (key < g_load(&d.key[root])) atomicMin(&d.key[root], key);
 }
 
-// FT tiles per workgroup: a root gets one atomic of each kind per workgroup
-// that holds some of its nodes, so a cluster that spans the lattice receives
-// ntiles / FT of them, one after the other; plain lattices take 64, batches
-// their 16-tile groups.  A key minimum is skipped when a plain read already
-// shows a key no larger (keys only decrease).
+// FT tiles per workgroup (16: the tile groups): a root gets one atomic of
+// each kind per workgroup that holds some of its nodes, so a cluster that
+// spans the lattice receives ntiles / FT of them, one after the other.  A key
+// minimum is skipped when a plain read already shows a key no larger (keys
+// only decrease).
 template <uint32_t FT>
 __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group) {
     __shared__ uint32_t hk[kHashSlots];
@@ -969,7 +976,7 @@ __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group)
 #pragma unroll
     for (uint32_t q = 0; q < 4u; ++q) {
         const uint32_t tile = g0 + wv + 4u * (4u * quad + q);
-        const uint32_t v = d.nk[pc][min(tile, d.ntiles - 1u)];  // issued unconditionally
+        const uint32_t v = nk_either(d, pc, min(tile, d.ntiles - 1u));  // issued unconditionally
         nkq[q] = tile < d.ntiles ? min(v, 252u) : 0u;
     }
     const uint32_t pre1 = nkq[0], pre2 = pre1 + nkq[1], pre3 = pre2 + nkq[2], tot = pre3 + nkq[3];
@@ -1010,18 +1017,25 @@ __device__ __forceinline__ void flatten_body(const Dev &d, const uint32_t group)
     }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < (uint32_t)kHashSlots; i += 256u) {
-        const uint32_t k = hk[i];
-        if (k != kEmpty) {
-            atomicAdd(&d.nsize[k], hv[i]);
-            if (hm[i] < g_load(&d.key[k])) atomicMin(&d.key[k], hm[i]);
-        }
+    // each thread flushes kHashSlots / 256 slots; the current keys of all its
+    // roots are read before any atomic so that those loads overlap
+    constexpr uint32_t kPer = (uint32_t)kHashSlots / 256u;
+    uint32_t fk[kPer], fm[kPer];
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) fk[j] = hk[threadIdx.x + 256u * j];
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) fm[j] = fk[j] != kEmpty ? g_load(&d.key[fk[j]]) : 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+        if (fk[j] == kEmpty) continue;
+        const uint32_t i = threadIdx.x + 256u * j;
+        atomicAdd(&d.nsize[fk[j]], hv[i]);
+        if (hm[i] < fm[j]) atomicMin(&d.key[fk[j]], hm[i]);
     }
 }
 
-constexpr uint32_t kFlatTiles = 64;  // tiles per workgroup of k_flatten (plain lattices)
-
-__global__ __launch_bounds__(256) void k_flatten(Dev d) { flatten_body<kFlatTiles>(d, blockIdx.x); }
+template <uint32_t FT>
+__global__ __launch_bounds__(256) void k_flatten(Dev d) { flatten_body<FT>(d, blockIdx.x); }
 
 __global__ __launch_bounds__(256) void k_flatten_b(const Dev *devs, const uint32_t *map) {
     const uint32_t e = map[blockIdx.x];
@@ -1050,13 +1064,14 @@ __global__ __launch_bounds__(256) void k_relabel(Dev d) {
 // k_roots: new spin of every cross-tile cluster (Sec. 2.4) and the cluster
 // statistics of the workgroup's tiles -> group partial.
 // =====================================================================
+// RB: nodes a lane takes at once (see below).
+template <uint32_t RB>
 __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
     __shared__ uint32_t s_hist[33];
     __shared__ uint32_t s_cnt[kMaxQ];  // Potts value populations of the group's tiles
     __shared__ uint64_t s_red[4][5];
     if (threadIdx.x < 33u) s_hist[threadIdx.x] = 0u;
     if (threadIdx.x < (uint32_t)kMaxQ) s_cnt[threadIdx.x] = 0u;
-    __syncthreads();
     const uint64_t tsw = *d.tdev;
     const uint32_t t = (uint32_t)tsw, pc = (uint32_t)(tsw & 1u);
     const uint32_t *par = d.parent[pc];
@@ -1069,23 +1084,43 @@ __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
 #pragma unroll
     for (uint32_t q = 0; q < 4u; ++q) {
         const uint32_t tile = g0 + wv + 4u * q;
-        const uint32_t v = d.nk[pc][min(tile, d.ntiles - 1u)];
+        const uint32_t v = nk_either(d, pc, min(tile, d.ntiles - 1u));
         nkq[q] = tile < d.ntiles ? min(v, 252u) : 0u;
     }
     const uint32_t pre1 = nkq[0], pre2 = pre1 + nkq[1], pre3 = pre2 + nkq[2], tot = pre3 + nkq[3];
-    {
-        for (uint32_t i = lane; i < tot; i += 64u) {
+    __syncthreads();  // s_hist and s_cnt cleared
+    // every node (flattened: its parent is its root) stores its cluster's
+    // new spin, drawn from the cluster's smallest site (the root's key).  A
+    // lane takes up to RB nodes at once and issues all their parent loads,
+    // then all their key and size loads, so that the wavefront waits on two
+    // rounds of loads per batch rather than on two for every node: launches
+    // of a few workgroups per CU wait on those rounds; full ones hide them
+    // behind other wavefronts and run faster with RB = 1 (fewer registers).
+    constexpr uint32_t kRootBatch = RB;
+    for (uint32_t m0 = 0; 64u * m0 < tot; m0 += kRootBatch) {
+        uint32_t nd[kRootBatch], rt[kRootBatch], rk[kRootBatch], sz[kRootBatch];
+#pragma unroll
+        for (uint32_t j = 0; j < kRootBatch; ++j) {
+            const uint32_t i = lane + 64u * (m0 + j);
             const uint32_t q = (uint32_t)(i >= pre1) + (uint32_t)(i >= pre2) + (uint32_t)(i >= pre3);
             const uint32_t base = q == 0u ? 0u : q == 1u ? pre1 : q == 2u ? pre2 : pre3;
-            const uint32_t node = (g0 + wv + 4u * q) * kNodeSlots + (i - base);
-            // every node (flattened: its parent is its root) stores its
-            // cluster's new spin, drawn from the cluster's smallest site
-            const uint32_t root = par[node];
-            const uint32_t rkey = d.key[root];
-            d.rspin[node] = d.q ? potts_spin(rkey, t, d.q, d.seed_lo, d.seed_hi)
-                                : cluster_spin(rkey, t, d.seed_lo, d.seed_hi);
-            if (root == node) {
-                const uint32_t S = d.nsize[node];
+            nd[j] = i < tot ? (g0 + wv + 4u * q) * kNodeSlots + (i - base) : kEmpty;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kRootBatch; ++j) rt[j] = nd[j] != kEmpty ? par[nd[j]] : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < kRootBatch; ++j) {
+            rk[j] = nd[j] != kEmpty ? d.key[rt[j]] : 0u;
+            sz[j] = nd[j] != kEmpty && rt[j] == nd[j] ? d.nsize[nd[j]] : 0u;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kRootBatch; ++j) {
+            if (64u * (m0 + j) >= tot) break;  // wavefront-uniform
+            if (nd[j] == kEmpty) continue;
+            d.rspin[nd[j]] = d.q ? potts_spin(rk[j], t, d.q, d.seed_lo, d.seed_hi)
+                                 : cluster_spin(rk[j], t, d.seed_lo, d.seed_hi);
+            if (rt[j] == nd[j]) {
+                const uint32_t S = sz[j];
                 ++n;
                 mx = max(mx, (uint64_t)S);
                 sq += (uint64_t)S * S;
@@ -1146,11 +1181,15 @@ __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
     if (threadIdx.x < (uint32_t)kMaxQ) gp[GP_CNT + threadIdx.x] = s_cnt[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_roots(Dev d) { roots_body(d, blockIdx.x); }
+// Plain lattices of at least kRootsWide groups (32768 tiles) take RB = 1.
+constexpr uint32_t kRootsWide = 2048;
+
+template <uint32_t RB>
+__global__ __launch_bounds__(256) void k_roots(Dev d) { roots_body<RB>(d, blockIdx.x); }
 
 __global__ __launch_bounds__(256) void k_roots_b(const Dev *devs, const uint32_t *map) {
     const uint32_t e = map[blockIdx.x];
-    roots_body(devs[e >> kMapShift], e & kMapMask);
+    roots_body<4>(devs[e >> kMapShift], e & kMapMask);
 }
 
 // =====================================================================
@@ -1262,7 +1301,10 @@ __global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode
         else
             atomicAdd(&acc[tid], (unsigned long long)s_acc[tid]);
     }
-    __threadfence();
+    // device-scope atomics are performed where every XCD sees them: once each
+    // wavefront has seen its own complete, the count may go up, and the last
+    // workgroup reads the totals with device-scope loads (no cache fences)
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0u) {
         const unsigned long long old = atomicAdd(&acc[ACC_COUNT], 1ull);
@@ -1270,7 +1312,6 @@ __global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode
     }
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
     // the last workgroup: take the totals (one field per thread) and clear
     // the accumulator for the next fold
     if (tid < (uint32_t)GP_END) {
@@ -1662,11 +1703,14 @@ hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
         break;
     }
     case 2:  // flatten + cluster sizes
-        k_flatten<<<(d.ntiles + kFlatTiles - 1u) / kFlatTiles, 256, 0, s>>>(d);
+        k_flatten<kGroupTiles><<<d.ngroups, 256, 0, s>>>(d);
         if (d.labels) k_relabel<<<grid_for(n, 256, 65536), 256, 0, s>>>(d);
         break;
     case 3:  // spins of cross-tile clusters, statistics
-        k_roots<<<d.ngroups, 256, 0, s>>>(d);
+        if (d.ngroups >= kRootsWide)
+            k_roots<1><<<d.ngroups, 256, 0, s>>>(d);
+        else
+            k_roots<4><<<d.ngroups, 256, 0, s>>>(d);
         break;
     case 4:  // record
         k_record<<<(d.ngroups + kRecordGroups - 1) / kRecordGroups, 256, 0, s>>>(d, d.ngroups, 0);

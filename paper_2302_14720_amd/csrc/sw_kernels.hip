@@ -784,25 +784,37 @@ __device__ __forceinline__ void union_body(const Dev &d, const uint32_t tile, co
     const bool glob = dir == 0u ? ((tx % kUG) == kUG - 1u || tx + 1u == ntx)
                                 : ((ty % kUG) == kUG - 1u || ty + 1u == ntx);
     if (!glob) return;
-    const uint64_t bits = d.xb[2u * tile + dir];
-    if (bits == 0ull) return;
-    const uint32_t pc = (uint32_t)(*d.tdev & 1u);
-    uint32_t *par = d.parent[pc];
+    static_assert(TW <= 64, "one lane per edge position");
     const uint32_t nb = dir == 0u ? ty * ntx + (tx + 1u == ntx ? 0u : tx + 1u)
                                   : (ty + 1u == ntx ? 0u : ty + 1u) * ntx + tx;
     const uint8_t *eg = d.edge + (size_t)tile * 4u * TW;
     const uint8_t *egb = d.edge + (size_t)nb * 4u * TW;
-    // one lane per edge position (two passes of 32 lanes for 32-wide tiles)
-    for (uint32_t i = lane; i < (uint32_t)TW; i += 64u) {
-        const bool has = (bits >> i) & 1u;
-        const uint32_t a = tile * kNodeSlots + (dir == 0u ? eg[1 * TW + i] : eg[3 * TW + i]);
-        const uint32_t b = nb * kNodeSlots + (dir == 0u ? egb[0 * TW + i] : egb[2 * TW + i]);
-        // a run of bonds along the edge between the same two nodes needs one union
-        const uint32_t pa = __shfl_up(a, 1, 64), pb = __shfl_up(b, 1, 64);
-        const int ph = __shfl_up((int)has, 1, 64);
-        const bool dup = i > 0u && ph && pa == a && pb == b;
-        if (has && !dup) g_union(par, a, b);
+    // one lane per edge position; the bond bits, both sides' node bytes and
+    // the sweep parity are all loaded before any of them is waited on
+    const bool in = lane < (uint32_t)TW;
+    const uint32_t i = in ? lane : 0u;
+    const uint32_t an = dir == 0u ? eg[1 * TW + i] : eg[3 * TW + i];
+    const uint32_t bn = dir == 0u ? egb[0 * TW + i] : egb[2 * TW + i];
+    const uint64_t bits = d.xb[2u * tile + dir];
+    // (volatile: keeps the compiler from sinking the load to its first use)
+    const uint32_t pc = (uint32_t)(*(volatile const uint64_t *)d.tdev & 1u);
+    uint32_t *par = pc ? d.parent[1] : d.parent[0];
+    const bool has = in && ((bits >> i) & 1u);
+    const uint32_t a = tile * kNodeSlots + an, b = nb * kNodeSlots + bn;
+    // every union starts from the two nodes' parents (their group roots, or
+    // nearer the root); a bond whose parents equal those of the previous
+    // bond along the edge adds nothing, so only the first of such a run
+    // links (fewer lanes compete for the same roots' compare-and-swap)
+    uint32_t ra = 0u, rb = 0u;
+    if (has) {
+        ra = g_load(&par[a]);
+        rb = g_load(&par[b]);
     }
+    const uint64_t below = __ballot(has) & ((1ull << lane) - 1ull);
+    const int prev = below ? 63 - __clzll((long long)below) : (int)lane;
+    const uint32_t pra = (uint32_t)__shfl((int)ra, prev, 64), prb = (uint32_t)__shfl((int)rb, prev, 64);
+    const bool dup = below != 0ull && pra == ra && prb == rb;
+    if (has && !dup) g_union(par, ra, rb);
 }
 
 // =====================================================================

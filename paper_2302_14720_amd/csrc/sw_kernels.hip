@@ -1076,8 +1076,9 @@ __global__ __launch_bounds__(256) void k_relabel(Dev d) {
 // k_roots: new spin of every cross-tile cluster (Sec. 2.4) and the cluster
 // statistics of the workgroup's tiles -> group partial.
 // =====================================================================
-// RB: nodes a lane takes at once (see below).
-template <uint32_t RB>
+// RB: nodes a lane takes at once (see below).  AG: the group partial is
+// written with agent-scope stores, for a fold in the same launch.
+template <uint32_t RB, bool AG = false>
 __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
     __shared__ uint32_t s_hist[33];
     __shared__ uint32_t s_cnt[kMaxQ];  // Potts value populations of the group's tiles
@@ -1174,6 +1175,12 @@ __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
     }
     __syncthreads();
     uint64_t *gp = d.gpart + (size_t)group * kGroupPart;
+    auto put = [&](int f, uint64_t v) {
+        if constexpr (AG)
+            __hip_atomic_store(&gp[f], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            gp[f] = v;
+    };
     if (threadIdx.x == 0u) {
         uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
         for (int w = 0; w < 4; ++w) {
@@ -1183,26 +1190,16 @@ __device__ __forceinline__ void roots_body(const Dev &d, const uint32_t group) {
             a3 += s_red[w][3];
             a4 += s_red[w][4];
         }
-        gp[GP_N] = a0;
-        gp[GP_MAX] = a1;
-        gp[GP_SQ] = a2;
-        gp[GP_E] = a3;
-        gp[GP_M] = a4;
+        put(GP_N, a0);
+        put(GP_MAX, a1);
+        put(GP_SQ, a2);
+        put(GP_E, a3);
+        put(GP_M, a4);
     }
-    if (threadIdx.x < 33u) gp[GP_HIST + threadIdx.x] = s_hist[threadIdx.x];
-    if (threadIdx.x < (uint32_t)kMaxQ) gp[GP_CNT + threadIdx.x] = s_cnt[threadIdx.x];
+    if (threadIdx.x < 33u) put(GP_HIST + (int)threadIdx.x, s_hist[threadIdx.x]);
+    if (threadIdx.x < (uint32_t)kMaxQ) put(GP_CNT + (int)threadIdx.x, s_cnt[threadIdx.x]);
 }
 
-// Plain lattices of at least kRootsWide groups (32768 tiles) take RB = 1.
-constexpr uint32_t kRootsWide = 2048;
-
-template <uint32_t RB>
-__global__ __launch_bounds__(256) void k_roots(Dev d) { roots_body<RB>(d, blockIdx.x); }
-
-__global__ __launch_bounds__(256) void k_roots_b(const Dev *devs, const uint32_t *map) {
-    const uint32_t e = map[blockIdx.x];
-    roots_body<4>(devs[e >> kMapShift], e & kMapMask);
-}
 
 // =====================================================================
 // k_record: fold group partials (mode 0, end of a sweep) or tile partials
@@ -1216,16 +1213,29 @@ __global__ __launch_bounds__(256) void k_roots_b(const Dev *devs, const uint32_t
 constexpr uint32_t kRecordGroups = 64;   // group partials per k_record workgroup
 constexpr uint32_t kRecordTiles = 2048;  // tile partials per k_record workgroup
 
+// AG: the group partials were written in the same launch (agent-scope
+// stores), so they are read with agent-scope loads.
+template <bool AG = false>
 __device__ __forceinline__ void record_fold(const Dev &d, uint32_t begin, uint32_t end, int mode, uint64_t *s_acc) {
     const uint32_t tid = threadIdx.x;
     unsigned long long *a = reinterpret_cast<unsigned long long *>(s_acc);
     if (mode != 1) {
         const uint32_t f = tid & 63u, sub = tid >> 6;
         if (f < (uint32_t)GP_END) {
+            // four partials per round, their loads issued together (0 is
+            // the identity of both the sums and the maximum)
             uint64_t v = 0;
-            for (uint32_t item = begin + sub; item < end; item += 4u) {
-                const uint64_t x = d.gpart[(size_t)item * kGroupPart + f];
-                v = f == (uint32_t)GP_MAX ? max(v, x) : v + x;
+            for (uint32_t item = begin + sub; item < end; item += 16u) {
+                uint64_t x[4];
+#pragma unroll
+                for (uint32_t u = 0; u < 4u; ++u) {
+                    const uint32_t it = item + 4u * u;
+                    const uint64_t *src = &d.gpart[(size_t)min(it, end - 1u) * kGroupPart + f];
+                    const uint64_t y = AG ? __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *src;
+                    x[u] = it < end ? y : 0u;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < 4u; ++u) v = f == (uint32_t)GP_MAX ? max(v, x[u]) : v + x[u];
             }
             if (f == (uint32_t)GP_MAX)
                 atomicMax(&a[f], (unsigned long long)v);
@@ -1347,6 +1357,49 @@ __global__ __launch_bounds__(256) void k_record_b(const Dev *devs, const uint32_
     record_fold(d, 0u, mode != 1 ? d.ngroups : d.ntiles, mode, s_acc);
     __syncthreads();
     record_write(d, s_acc, mode);
+}
+
+// k_roots, and the record folded into the same launch: the last workgroup of
+// a lattice to write its group partial folds them all and writes the record
+// (one launch less per sweep).  The partials go out as agent-scope stores
+// and every wavefront waits for its own to complete before its workgroup
+// counts itself in, so the last one reads them all with agent-scope loads
+// (no cache fences).  Used where a lattice has few groups (the fold is one
+// workgroup's work) and for every replica of a batch.
+template <uint32_t RB>
+__device__ __forceinline__ void roots_fold_body(const Dev &d, const uint32_t group) {
+    __shared__ uint64_t s_acc[GP_END];
+    __shared__ int s_last;
+    roots_body<RB, true>(d, group);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(d.acc);
+    if (threadIdx.x == 0u) {
+        const unsigned long long old = atomicAdd(&acc[ACC_COUNT], 1ull);
+        s_last = old == (unsigned long long)d.ngroups - 1ull ? 1 : 0;
+    }
+    if (threadIdx.x < (uint32_t)GP_END) s_acc[threadIdx.x] = 0u;
+    __syncthreads();
+    if (!s_last) return;
+    if (threadIdx.x == 0u) __hip_atomic_store(&acc[ACC_COUNT], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    record_fold<true>(d, 0u, d.ngroups, 0, s_acc);
+    __syncthreads();
+    record_write(d, s_acc, 0);
+}
+
+// Plain lattices: up to kRootsFold groups the record is folded by k_roots;
+// from kRootsWide groups (32768 tiles) on, a lane takes one node at a time.
+constexpr uint32_t kRootsFold = 64;
+constexpr uint32_t kRootsWide = 2048;
+
+template <uint32_t RB>
+__global__ __launch_bounds__(256) void k_roots(Dev d) { roots_body<RB>(d, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_roots_fold(Dev d) { roots_fold_body<4>(d, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_roots_b(const Dev *devs, const uint32_t *map) {
+    const uint32_t e = map[blockIdx.x];
+    roots_fold_body<4>(devs[e >> kMapShift], e & kMapMask);
 }
 
 // =====================================================================
@@ -1718,14 +1771,17 @@ hipError_t launch_stage(const Dev &d, int stage, hipStream_t s) {
         k_flatten<kGroupTiles><<<d.ngroups, 256, 0, s>>>(d);
         if (d.labels) k_relabel<<<grid_for(n, 256, 65536), 256, 0, s>>>(d);
         break;
-    case 3:  // spins of cross-tile clusters, statistics
+    case 3:  // spins of cross-tile clusters, statistics (and the record, on few groups)
         if (d.ngroups >= kRootsWide)
             k_roots<1><<<d.ngroups, 256, 0, s>>>(d);
-        else
+        else if (d.ngroups > kRootsFold)
             k_roots<4><<<d.ngroups, 256, 0, s>>>(d);
+        else
+            k_roots_fold<<<d.ngroups, 256, 0, s>>>(d);
         break;
-    case 4:  // record
-        k_record<<<(d.ngroups + kRecordGroups - 1) / kRecordGroups, 256, 0, s>>>(d, d.ngroups, 0);
+    case 4:  // record (folded by k_roots on few groups)
+        if (d.ngroups > kRootsFold)
+            k_record<<<(d.ngroups + kRecordGroups - 1) / kRecordGroups, 256, 0, s>>>(d, d.ngroups, 0);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1787,11 +1843,10 @@ hipError_t launch_batch_stage(const BatchDev &b, int stage, hipStream_t s) {
     case 2:
         k_flatten_b<<<b.ngroups, 256, 0, s>>>(b.devs, b.gmap);
         break;
-    case 3:
+    case 3:  // and the records
         k_roots_b<<<b.ngroups, 256, 0, s>>>(b.devs, b.gmap);
         break;
-    case 4:
-        k_record_b<<<b.n, 256, 0, s>>>(b.devs, b.rmap, 0);
+    case 4:  // (folded by k_roots_b)
         break;
     default:
         return hipErrorInvalidValue;

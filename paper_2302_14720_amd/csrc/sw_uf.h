@@ -55,19 +55,23 @@ __device__ __forceinline__ uint32_t g_load(uint32_t *p) {
 __device__ __forceinline__ void g_store(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Union in global memory.  Both finds advance together (their loads
-// overlap), each with path halving: an entry is re-pointed at its
-// grandparent, which is an ancestor whatever other unions did meanwhile.
+// Union in global memory.  Both finds advance together, one level per
+// round of loads (their loads overlap), with path splitting: every entry
+// passed is re-pointed at its grandparent, which is an ancestor whatever
+// other unions did meanwhile.  The two paths meeting below their roots (a
+// common parent) already shows one set.
 __device__ __forceinline__ void g_union(uint32_t *par, uint32_t a, uint32_t b) {
     while (true) {
-        while (true) {
-            const uint32_t pa = g_load(&par[a]), pb = g_load(&par[b]);
-            if (pa == a && pb == b) break;
+        uint32_t pa = g_load(&par[a]), pb = g_load(&par[b]);
+        while (pa != a || pb != b) {
+            if (pa == pb) return;
             const uint32_t ga = g_load(&par[pa]), gb = g_load(&par[pb]);
             if (ga != pa) g_store(&par[a], ga);
             if (gb != pb) g_store(&par[b], gb);
-            a = ga;
-            b = gb;
+            a = pa;
+            b = pb;
+            pa = ga;
+            pb = gb;
         }
         if (a == b) return;
         if (a > b) { const uint32_t tmp = a; a = b; b = tmp; }

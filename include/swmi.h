@@ -142,10 +142,12 @@ int sw_sweep(sw_sim *sim, int64_t n);
  * kernels, same results, same records), but launches the kernels one by one
  * with HIP events between them on the sim's stream and waits after each
  * sweep.  ms[0..4] receive the average duration in milliseconds of the five
- * kernels of a sweep -- 0: bonds + tile-local clusters (Sec. 2.1, 2.3),
+ * stages of a sweep -- 0: bonds + tile-local clusters (Sec. 2.1, 2.3),
  * 1: cross-tile unions, 2: flattening and cluster sizes, 3: spins of
- * cross-tile clusters (Sec. 2.4) and statistics, 4: the record (Sec. 2.5) --
- * and ms[5] the closing pass that writes final spins and measures them.
+ * cross-tile clusters (Sec. 2.4) and statistics, 4: the record (Sec. 2.5;
+ * on lattices of at most 64 groups of 16 tiles stage 3 writes the record
+ * and stage 4 launches nothing, so ms[4] is the events' own cost) -- and
+ * ms[5] the closing pass that writes final spins and measures them.
  * nk (the length of ms) must be >= 6; extra entries are zeroed. */
 int sw_profile(sw_sim *sim, int64_t n, double *ms, int32_t nk);
 
@@ -258,8 +260,9 @@ const char *sw_last_error(void);
  * of a sweep (Sec. 2) runs once over all replicas of a launch group (the
  * replicas with one tile width and model), so a sweep of the whole batch
  * costs a handful of kernel launches (replayed from one captured graph)
- * instead of six per replica.  The cross-tile merge of Sec. 2.3 runs either
- * globally (four launches over all such replicas) or, for a replica of at
+ * instead of five or six per replica.  The cross-tile merge of Sec. 2.3 runs
+ * either globally (four launches over all such replicas, the record folded
+ * into the last) or, for a replica of at
  * most 16 tiles, entirely in one workgroup's LDS (one launch for all such
  * replicas: SW_MERGE_LDS).  Replica r has its own L[r], beta[r], J[r],
  * seed[r] and its own records; its spins, clusters and records are bit for

@@ -1,6 +1,6 @@
 // sw_internal.h -- device-state layout and kernel entry points of libswmi.
 //
-// One sweep (paper Sec. 2) runs as five kernels on the sim's stream:
+// One sweep (paper Sec. 2) runs as these kernels on the sim's stream:
 //   k_tile    bond formation (Sec. 2.1) and cluster formation (Sec. 2.3)
 //             inside one 64x64 (or 32x32) tile per workgroup, in LDS; new
 //             spins (Sec. 2.4) of clusters that stay inside the tile; the
@@ -14,7 +14,9 @@
 //   k_flatten point every node at its root; add node sizes into the roots
 //             and reduce node keys to the cluster's smallest site.
 //   k_roots   new spin of each cross-tile cluster, cluster statistics.
-//   k_record  fold partial statistics into the per-sweep record ring.
+//   k_record  fold partial statistics into the per-sweep record ring (on
+//             lattices of at most 64 groups the last k_roots workgroup
+//             folds them, and the sweep is four launches).
 // Spins are double-buffered by sweep parity.  A written spin byte is either
 // the final spin (0x01 = +1, 0xFF = -1) or 2 + k, a reference to node k of
 // the tile, resolved through the node tables of that sweep when the byte is
@@ -92,8 +94,9 @@ hipError_t launch_sweep(const Dev &d, hipStream_t s);
 hipError_t launch_resolve(const Dev &d, hipStream_t s);
 
 // Batched sweeps: each kernel of a sweep runs once over a table of
-// independent lattices (replicas), each with its own Dev, so a batch costs
-// five launches per sweep whatever its size.  The maps list the work units
+// independent lattices (replicas), each with its own Dev, so the launches
+// per sweep do not grow with the batch (five per launch group under the
+// global merge, the record folded by k_roots_b).  The maps list the work units
 // of every replica: entry = replica << kMapShift | unit.
 constexpr uint32_t kMapShift = 20;
 constexpr uint32_t kMapMask = (1u << kMapShift) - 1u;

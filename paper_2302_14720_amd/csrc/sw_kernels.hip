@@ -1346,8 +1346,10 @@ __global__ __launch_bounds__(256) void k_record(Dev d, uint32_t nitems, int mode
     record_write(d, s_acc, mode);
 }
 
-// Batched record: one workgroup per replica folds all of that replica's
-// partials itself, so no cross-workgroup accumulator is needed.
+// Batched record of the tile partials at the end of a resolve (mode 1): one
+// workgroup per replica folds all of that replica's partials itself, so no
+// cross-workgroup accumulator is needed (the group partials of a sweep are
+// folded by k_roots_b).
 __global__ __launch_bounds__(256) void k_record_b(const Dev *devs, const uint32_t *rmap, int mode) {
     __shared__ uint64_t s_acc[GP_END];
     const Dev &d = devs[rmap[blockIdx.x]];

@@ -828,7 +828,6 @@ template <int TW>
 __device__ __forceinline__ void ulocal_body(const Dev &d, const uint32_t ugroup) {
     constexpr uint32_t NG = kUG * kUG;
     __shared__ uint32_t s_p[NG * kNodeSlots];
-    __shared__ uint32_t s_nk[NG];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const uint32_t pc = (uint32_t)(*d.tdev & 1u);
     const uint32_t ntx = d.ntx, ngx = (ntx + kUG - 1u) / kUG;
@@ -858,8 +857,13 @@ __device__ __forceinline__ void ulocal_body(const Dev &d, const uint32_t ugroup)
         ua[it] = ta * kNodeSlots + (isn ? ea[3 * TW + i] : ea[1 * TW + i]);
         ub[it] = tb * kNodeSlots + (isn ? eb[2 * TW + i] : eb[0 * TW + i]);
     }
-    if (tid < NG) s_nk[tid] = valid(tid) ? min(d.nk[pc][tile_of(tid)], 252u) : 0u;
-    for (uint32_t i = tid; i < NG * kNodeSlots; i += 256u) s_p[i] = i;
+    // 16 threads per tile of the group (thread tid: tile tid / 16, node
+    // slots tid % 16 + 16 m), so that the slots of every tile's nodes, and
+    // only those, are set up and later resolved in about nk / 16 steps
+    static_assert(NG * 16u == 256u, "16 threads per tile");
+    const uint32_t mt = tid >> 4, mk = tid & 15u;
+    const uint32_t nkt = valid(mt) ? min(d.nk[pc][tile_of(mt)], 252u) : 0u;
+    for (uint32_t k = mk; k < nkt; k += 16u) s_p[mt * kNodeSlots + k] = mt * kNodeSlots + k;
     __syncthreads();
 #pragma unroll
     for (uint32_t it = 0; it < NIT; ++it) {
@@ -874,11 +878,11 @@ __device__ __forceinline__ void ulocal_body(const Dev &d, const uint32_t ugroup)
     __syncthreads();
 
     uint32_t *par = d.parent[pc];
-    for (uint32_t li = tid; li < NG * kNodeSlots; li += 256u) {
-        const uint32_t t = li / kNodeSlots, k = li % kNodeSlots;
-        if (k >= s_nk[t]) continue;
+    const uint32_t gt = tile_of(mt);
+    for (uint32_t k = mk; k < nkt; k += 16u) {
+        const uint32_t li = mt * kNodeSlots + k;
         const uint32_t r = lds_root(s_p, li);
-        if (r != li) par[tile_of(t) * kNodeSlots + k] = tile_of(r / kNodeSlots) * kNodeSlots + r % kNodeSlots;
+        if (r != li) par[gt * kNodeSlots + k] = tile_of(r / kNodeSlots) * kNodeSlots + r % kNodeSlots;
     }
 }
 

@@ -92,6 +92,15 @@ __device__ __forceinline__ void lds_union_lo(uint32_t *par, uint32_t a, uint32_t
     }
 }
 
+// Low half (the parent) and high half of the word at byte offset off, each
+// read on its own (16-bit loads; the halves are little-endian).
+__device__ __forceinline__ uint32_t lo16_at(uint32_t *base, uint32_t off) {
+    return *reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(base) + off);
+}
+__device__ __forceinline__ uint32_t hi16_at(uint32_t *base, uint32_t off) {
+    return *reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(base) + off + 2u);
+}
+
 // Root (byte offset) of the word at byte offset a once the unions are done.
 __device__ __forceinline__ uint32_t lds_root_b(uint32_t *par, uint32_t a) {
     while (true) {
@@ -515,7 +524,13 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     uint32_t rootmask = 0u;
     {
         const bool edge_row = ly == 0u || ly == TW - 1u;
-        const Row after = (Row)(B0 >> 1);  // bit x: a run starts at x + 1
+        // where the run holding the lane's last site ends: the first run
+        // start past the lane's 16 sites, or the row's end
+        uint32_t end_out = (uint32_t)TW;
+        if (x0 + 16u < (uint32_t)TW) {
+            const Row past = (Row)(B0 >> (x0 + 16u));
+            if (past) end_out = x0 + 16u + (uint32_t)__builtin_ctzll((unsigned long long)past);
+        }
         // lengths of consecutive runs with the same root are summed in a
         // register (at most TW per lane) and added with one atomic
         uint32_t acc_root = 0u, acc_len = 0u;
@@ -533,12 +548,8 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
                 const uint32_t rsite = root / 4u - root / (4u * PS);
                 atomicOr(&s_bf[rsite >> 5], 1u << (rsite & 31u));
             }
-            const Row nx = (Row)(after >> (x0 + i));  // bit j: the next run starts j + 1 sites on
-            uint32_t len;
-            if constexpr (TW == 64)
-                len = nx ? (uint32_t)__ffsll((unsigned long long)nx) : (uint32_t)TW - (x0 + i);
-            else
-                len = nx ? (uint32_t)__ffs((int)nx) : (uint32_t)TW - (x0 + i);
+            // the run goes on to the lane's next run start, or past the lane
+            const uint32_t len = (m ? (uint32_t)__ffs((int)m) - 1u + x0 : end_out) - (x0 + i);
             if (root != acc_root && acc_len != 0u)
                 __hip_atomic_fetch_add(word_at(s_par, acc_root), acc_len << 16, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -609,7 +620,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
             const uint32_t q = (uint32_t)__ffs((int)rootmask) - 1u;
             rootmask &= rootmask - 1u;
             const uint32_t root = rowbase + x0 + q;
-            const uint32_t S = s_par[root] >> 16;
+            const uint32_t S = hi16_at(s_par, 4u * root);
             uint32_t code;
             if ((bmask >> q) & 1u) {
                 const uint32_t k = kbase + __popc(bmask & ((1u << q) - 1u));
@@ -648,8 +659,8 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             if ((st >> q) & 1u) cur = rowoff + 4u * (x0 + (uint32_t)q);
-            const uint32_t root = *word_at(s_par, cur) & 0xFFFFu;
-            const uint32_t code = *word_at(s_par, root) >> 16;
+            const uint32_t root = lo16_at(s_par, cur);
+            const uint32_t code = hi16_at(s_par, root);
             out[q >> 2] |= code << (8 * (q & 3));
         }
     }
@@ -660,7 +671,7 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             if ((st >> q) & 1u) cur = rowoff + 4u * (x0 + (uint32_t)q);
-            const uint32_t root = *word_at(s_par, cur) & 0xFFFFu;
+            const uint32_t root = lo16_at(s_par, cur);
             const uint32_t rsite = root / 4u - root / (4u * PS);
             const uint32_t code = (out[q >> 2] >> (8 * (q & 3))) & 0xFFu;
             lab[q] = (code >= CB && code < CB + 252u) ? (0x80000000u | (tile * kNodeSlots + code - CB))
@@ -755,8 +766,12 @@ __device__ __forceinline__ void tile_body(const Dev &d, const uint32_t tile) {
     }
 }
 
+// 64-wide tiles: at most 64 VGPRs, so that the 8 workgroups per CU that the
+// LDS allows (8 wavefronts per SIMD) all fit.
+constexpr int kTileWavesPerEU = 8;
+
 template <int TW, bool POTTS = false>
-__global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
+__global__ __launch_bounds__(TW *TW / 16, TW == 64 ? kTileWavesPerEU : 1) void k_tile(Dev d) {
     tile_body<TW, POTTS>(d, tile_of_block(blockIdx.x, d.ntiles));
 }
 
@@ -764,7 +779,7 @@ __global__ __launch_bounds__(TW *TW / 16) void k_tile(Dev d) {
 // entries replica << kMapShift | unit index), so every replica's bits are
 // those of its own plain sweep.
 template <int TW, bool POTTS = false>
-__global__ __launch_bounds__(TW *TW / 16) void k_tile_b(const Dev *devs, const uint32_t *map) {
+__global__ __launch_bounds__(TW *TW / 16, TW == 64 ? kTileWavesPerEU : 1) void k_tile_b(const Dev *devs, const uint32_t *map) {
     const uint32_t e = map[tile_of_block(blockIdx.x, gridDim.x)];
     tile_body<TW, POTTS>(devs[e >> kMapShift], e & kMapMask);
 }

@@ -105,6 +105,21 @@ def test_L1024_three_temperatures(beta, seed):
         assert np.array_equal(s.spins(), sp)
 
 
+@pytest.mark.parametrize("L", [2048, 2112])
+def test_record_fold_boundary(L):
+    """L = 2048: 1024 tiles, 64 groups of 16, the largest lattice whose last
+    k_roots workgroup folds the record; L = 2112: 1089 tiles, 69 groups (the
+    last one ragged), folded by k_record.  Cold and hot starts, every record
+    and the final spins against the oracle."""
+    for cold, seed in ((True, 31), (False, 32)):
+        n = 4
+        ref, sp = _oracle_run(L, BETA_C, seed, n, cold=cold)
+        with _sim(L, BETA_C, seed, init=sw.SW_INIT_COLD if cold else sw.SW_INIT_HOT) as s:
+            s.sweep(n)
+            _assert_records(s.series(0, n), ref, f"L={L} cold={cold}")
+            assert np.array_equal(s.spins(), sp)
+
+
 def test_cold_start_giant_cluster():
     L, seed, n = 256, 3, 10
     ref, sp = _oracle_run(L, BETA_C, seed, n, cold=True)

@@ -151,3 +151,27 @@ def test_tile_path_large_lattice(q):
         assert np.array_equal(s.spins(), state)
         assert np.all(recs["e_sum"] <= 2 * L * L) and np.all(recs["m_sum"] >= L * L // q)
         assert np.all(recs["hist_log2"].sum(axis=1) == recs["n_clusters"])
+
+
+def test_tile_path_headline_lattice_one_step():
+    """The benchmark's Potts leg (q = 3 at ln(1 + sqrt 3), L = 16384, 64-wide
+    tiles, hot start seed 11): the GPU chain runs to sweep 10, and sweep 10
+    is compared with one oracle sweep from the GPU's own state -- record,
+    spins and every site's canonical label."""
+    L, q, seed, t = 16384, 3, 11, 10
+    beta = math.log(1.0 + math.sqrt(q))
+    T = oracle.potts_threshold(beta, 1.0)
+    with _potts_tile(L, q, beta, seed, flags=sw.SW_FLAG_LABELS) as s:
+        assert s.threshold == T and s.tile == 64
+        s.sweep(t)
+        state = s.spins()
+        s.sweep(1)
+        rec = s.series(t, 1)
+        final = s.spins()
+        lab = s.labels()
+    ref, olab = oracle.potts_sweep(L, 1.0, T, q, seed, t, state)
+    assert rec[0].tobytes() == ref.tobytes()
+    assert np.array_equal(final, state)
+    del state, final
+    bad = np.nonzero(lab != olab)[0]
+    assert bad.size == 0, f"labels differ at {bad.size} sites, first {bad[0]}"

@@ -145,6 +145,25 @@ def test_full_size_properties(path):
         assert abs(e.mean() - want) < 6 * err, (e.mean(), want, err)
 
 
+@pytest.mark.parametrize("q,beta", [(0, BETA_C3), (3, 0.5505)])
+def test_benchmark_lattice_one_step(q, beta):
+    """The benchmark's cubic legs (512^3 on bricks, hot start seed 13, Ising
+    at 0.2216544 and q = 3 Potts at 0.5505): the GPU chain runs to sweep 3,
+    and sweep 3 is compared with one oracle sweep from the GPU's own state
+    (record and spins)."""
+    L, seed, t = 512, 13, 3
+    T = _threshold(q, beta)
+    with _cube(L, beta, seed, q=q) as s:
+        s.sweep(t)
+        state = s.spins()
+        s.sweep(1)
+        rec = s.series(t, 1)
+        final = s.spins()
+    ref, _, _ = oracle.cubic_sweep(L, 1.0, T, q, seed, t, state)
+    assert rec[0].tobytes() == ref.tobytes()
+    assert np.array_equal(final, state)
+
+
 def test_cubic_configuration_errors():
     cases = [
         dict(dims=3, flags=0, L=40),                         # not a multiple of 16

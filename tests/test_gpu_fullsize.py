@@ -93,6 +93,29 @@ def test_L16384_one_step(cold, t):
         assert bad.size == 0, f"labels differ at {bad.size} sites, first {bad[0]}"
 
 
+def test_L16384_critical_energy():
+    """The benchmark configuration against an exact value: the mean of
+    e_sum / N over sweeps 200..999 of the hot-start chain at beta_c must lie
+    within 3e-4 of Kaufman's exact energy of the 16384 x 16384 torus
+    (1.4142516, 3.8e-5 above Onsager's sqrt(2)); block means of such chains
+    scatter by about 5e-5 over 800 sweeps.  The first record (one sweep
+    from the infinite-temperature start) must be far from it."""
+    import exact
+
+    L, seed = 16384, 4
+    N = L * L
+    with sw.Sim(L, BETA_C, 1.0, seed) as s:
+        s.sweep(1000)
+        recs = s.series(0, 1000)
+    _invariants(recs, N, "L=16384 1000 sweeps")
+    e = recs["e_sum"].astype(np.float64) / N
+    want = -exact.kaufman_energy(BETA_C, L, dps=30)
+    print(f"\n[case] L=16384 beta_c: e_sum/N mean {e[200:].mean():.7f}, exact {want:.7f}, first {e[0]:.4f}",
+          flush=True)
+    assert abs(e[200:].mean() - want) < 3e-4
+    assert e[0] < 1.2
+
+
 def test_grid_batch_5000_sweeps():
     """The 256-replica grid for its full 5000 sweeps as one batch; one
     replica of each side against a plain sim run alone (last 64 records and
